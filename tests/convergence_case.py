@@ -1,0 +1,91 @@
+"""The coupled convergence problem of Sec. 5.1, set up for the oracle.
+
+Fully periodic cube of side L = 0.1 m centred on the origin; cosine E and H
+fields of eq:convergeE / eq:convergeH placed at their Yee locations;
+Gaussian bumps in sigma, eps, Ms, alpha and gamma at cell centres; Mx = Ms,
+no bias; CFL 0.9 on the vacuum light speed; runs of 5 * N/32 steps reach the
+same physical time.  Errors follow the paper: mean absolute difference
+between a run and the next finer one restricted to the coarse locations
+(4 fine faces per coarse face, 2 fine edges per coarse edge).
+"""
+import math
+
+import numpy as np
+
+import workloads as W
+from oracle import Simulation
+
+L = 0.1
+
+
+def build(N, tol=1e-6, side=L):
+    """`side` is the edge length of the periodic cube centred on the origin."""
+    d = (side / N,) * 3
+    dt = W.cfl_dt(0.9, *d)
+    xn = np.arange(N) * d[0] - side / 2        # node coordinates
+    xc = xn + d[0] / 2                          # cell-centre coordinates
+    X, Y, Z = np.meshgrid(xc, xc, xc, indexing="ij")
+    g = np.exp(-1000.0 * (X**2 + Y**2 + Z**2))
+    host = lambda a: np.ascontiguousarray(a.transpose(2, 1, 0))
+    m0 = np.zeros((3, N, N, N))
+    m0[0] = 1.0
+    sim = Simulation((N,) * 3, d, dt, eps_r=host(1 + g), sigma=host(0.1 * g),
+                     Ms=host(1e4 * (1 + g)), alpha=host(0.5 * (1 + g)),
+                     gamma=host(-1.759e11 * (1 + g)), m0_dir=m0,
+                     periodic=(True, True, True), tol=tol, max_iter=100)
+    k = 20 * math.pi
+    e0, h0 = 1e6, 1e6 / (120 * math.pi)
+    ones = np.ones((N, N, N))
+    # ijk-indexed placements
+    Ex = e0 * np.cos(k * xn)[None, None, :] * ones      # cos(20 pi z), z at nodes
+    Ey = e0 * np.cos(k * xn)[:, None, None] * ones      # cos(20 pi x), x at nodes
+    Ez = e0 * np.cos(k * xn)[None, :, None] * ones      # cos(20 pi y), y at nodes
+    Hx = h0 * np.cos(k * xc)[None, :, None] * ones      # cos(20 pi y), y at cell centres
+    Hy = h0 * np.cos(k * xc)[None, None, :] * ones      # cos(20 pi z), z at cell centres
+    Hz = h0 * np.cos(k * xc)[:, None, None] * ones      # cos(20 pi x), x at cell centres
+    sim.set_fields(E=[host(a) for a in (Ex, Ey, Ez)], H=[host(a) for a in (Hx, Hy, Hz)])
+    return sim
+
+
+def run(N, side=L):
+    sim = build(N, side=side)
+    sim.step(5 * N // 32)
+    out = {}
+    for nm in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):
+        out[nm] = sim.field(nm).transpose(2, 1, 0)
+    for f in "xyz":
+        for c in "xyz":
+            out["M" + f + c] = sim.field("M" + f + c).transpose(2, 1, 0)
+    return out
+
+
+def restrict_edge(a, comp):
+    """Mean of the 2 fine edges along `comp` under each coarse edge."""
+    sl0 = [slice(0, None, 2)] * 3
+    sl1 = [slice(0, None, 2)] * 3
+    sl1[comp] = slice(1, None, 2)
+    return 0.5 * (a[tuple(sl0)] + a[tuple(sl1)])
+
+
+def restrict_face(a, fam):
+    """Mean of the 4 fine faces covering each coarse face of family `fam`."""
+    u, v = [ax for ax in range(3) if ax != fam]
+    acc = 0.0
+    for du in (0, 1):
+        for dv in (0, 1):
+            sl = [slice(0, None, 2)] * 3
+            sl[u] = slice(du, None, 2)
+            sl[v] = slice(dv, None, 2)
+            acc = acc + a[tuple(sl)]
+    return 0.25 * acc
+
+
+def l1_error(coarse, fine):
+    err = {}
+    for nm, a in coarse.items():
+        if nm[0] == "E":
+            r = restrict_edge(fine[nm], "xyz".index(nm[1]))
+        else:
+            r = restrict_face(fine[nm], "xyz".index(nm[1]))
+        err[nm] = float(np.mean(np.abs(r - a)))
+    return err

@@ -1,0 +1,164 @@
+"""Throughput of the coupled Maxwell-LLG step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload filter512] [--no-cpu]
+
+A step is one full coupled time step (Step 1 H-M sub-step, Step 2 E update
+with the soft source, Step 3 H-M sub-step, probe sampling) on the
+512 x 256 x 256 tunable-filter-like grid (33.5M cells, two ferrite bars,
+16 lossy dielectric boxes), fields resident in HBM.  The FP64 run is the
+headline; the FP32 bulk mode runs the same workload afterwards and its
+fields are compared with the FP64 run's.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per cell for one launch of each bulk kernel
+# (read E(3) + H(3), write H(3) for h_bulk; read E(3) + H(3) + eps + sigma,
+# write E(3) for e_update), per storage element size
+BYTES_PER_CELL = {"h_bulk": 9, "e_update": 11}
+
+
+def run_gpu(cfg, precision, steps, warmup):
+    import torch
+    import paper_2103_12819_amd as mm
+
+    sim = mm.from_config(cfg, precision=precision)
+    info = sim.info()
+    stream = torch.cuda.current_stream()
+    sim.step(warmup)
+    sim.sync()
+    sim.profile(True)
+    sim.profile_read()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    sim.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    kern = sim.profile_read()
+    sim.profile(False)
+    iters = sim.stats()
+    sim.sync()
+    return sim, info, ms, wall, kern, iters
+
+
+def cpu_baseline(budget_s=15.0):
+    """The oracle on the 128x64x64 crop of the same grid, as many steps as fit
+    in the time budget (at least 2)."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from oracle import from_config as oracle_from_config
+    cfg = W.filter_crop(seed=0, steps=1)
+    sim = oracle_from_config(cfg)
+    sim.step(1)              # first step outside the timing (allocation warm-up)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        sim.step(1)
+        n += 1
+        el = time.perf_counter() - t0
+        if (el > budget_s and n >= 2) or n >= 2000:
+            break
+    return {"value": cfg.cells * n / el / 1e6, "unit": "Mcell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"oracle (numpy FP64, 1 thread) on the 128x64x64 crop of the filter grid, "
+                      f"{n} steps in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="filter512")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is described in the design notes only)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+
+    cfg = W.CONFIGS[args.workload]()
+    cells = cfg.cells
+    print(f"[bench] {cfg.name} {cfg.n} fp64: warmup {args.warmup}, steps {args.steps}", flush=True)
+    sim64, info64, ms64, wall64, kern64, it64 = run_gpu(cfg, "fp64", args.steps, args.warmup)
+    per_step = ms64 / args.steps
+    value = cells * args.steps / (ms64 / 1e3) / 1e6
+    # dominant kernel and its roofline
+    dom = max(("h_bulk", "e_update"), key=lambda k: kern64[k][0])
+    dom_ms, dom_n = kern64[dom]
+    avg_s = dom_ms / dom_n / 1e3
+    algo_bytes = BYTES_PER_CELL[dom] * 8 * cells
+    achieved = algo_bytes / avg_s / 1e9
+    print(f"[bench] fp64 {per_step:.3f} ms/step, {value:.1f} Mcell/s, kernels {kern64}", flush=True)
+
+    out = {
+        "metric": "coupled Mcell-updates/s (FP64; FP32 bulk mode alongside with its L2 error vs FP64)",
+        "value": round(value, 2),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name} {cfg.n[0]}x{cfg.n[1]}x{cfg.n[2]} ({cells} cells), "
+                               "2 ferrite bars + 16 seeded lossy dielectric boxes, Jz port, PEC",
+                   "cells": cells, "magnetic_faces": info64["n_mag"], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 4),
+                     "algorithmic_bytes_per_launch": algo_bytes},
+        "kernels_fp64_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kern64.items()},
+        "iterations_per_substep": {str(k): int(v) for k, v in
+                                   zip(*np.unique(it64[-2 * args.steps:], return_counts=True))},
+    }
+    if not args.no_fp32:
+        print("[bench] fp32 run", flush=True)
+        sim32, info32, ms32, wall32, kern32, it32 = run_gpu(cfg, "fp32", args.steps, args.warmup)
+        v32 = cells * args.steps / (ms32 / 1e3) / 1e6
+        l2 = {}
+        for nm in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):
+            a, b = sim32.field(nm), sim64.field(nm)
+            l2[nm] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        out["fp32"] = {"value": round(v32, 2), "ms_per_step": round(ms32 / args.steps, 4),
+                       "rel_l2_vs_fp64_after_steps": {k: float(f"{v:.3e}") for k, v in l2.items()},
+                       "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kern32.items()}}
+        print(f"[bench] fp32 {ms32 / args.steps:.3f} ms/step, {v32:.1f} Mcell/s", flush=True)
+        sim32.close()
+    sim64.close()
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * mm.h -- C ABI of the MI355X coupled Maxwell-LLG time stepper.
+ *
+ * Method: Yao, Jambunathan, Zeng & Nonaka, "A Massively Parallel Time-Domain
+ * Coupled Electrodynamics-Micromagnetics Solver": the second-order coupled
+ * scheme of Sec. 3.2.2 on the Yee grid of Sec. 3.1 -- per step an H-M
+ * half step (Step 1), the E update (Step 2), and a second H-M half step
+ * (Step 3).
+ *
+ * Conventions (all entry points):
+ *   - SI units throughout.
+ *   - A "cell map" is a host array of nx*ny*nz doubles, x fastest
+ *     (element (i,j,k) at i + nx*(j + ny*k)).
+ *   - Field arrays use their staggered extents, x fastest.  Per axis a the
+ *     node count is n_a+1 on a PEC axis and n_a on a periodic axis:
+ *       Ex: nx   x NY x NZ      Hx: NX x ny x nz
+ *       Ey: NX x ny   x NZ      Hy: nx x NY x nz
+ *       Ez: NX x NY x nz        Hz: nx x ny x NZ     (NX = x node count, ...)
+ *     M on the faces of family f (normal to axis f) has H_f's extent; all
+ *     three components are stored per face (Sec. 3.1).
+ *   - Every entry point returns an mm_status; 0 is success.  Argument errors
+ *     are returned immediately.  Conditions found on the device (a sub-step
+ *     that hit max_iter, a non-finite residual) are recorded in a sticky
+ *     word and returned by the next synchronising call (mm_sync, mm_probe,
+ *     mm_get_field, mm_stats); the time stepping itself continues.
+ *   - A context is not thread-safe.  Separate contexts are independent.
+ *   - All device work of a context is enqueued on the stream given in
+ *     mm_options (NULL = the null stream).
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MM_OK = 0,
+  MM_EINVAL = -1,      /* bad argument: shape, dt above the CFL limit, Ms < 0, tol <= 0 ... */
+  MM_ENOMEM = -2,      /* device or host allocation failed */
+  MM_EDEVICE = -3,     /* a HIP call failed */
+  MM_ENOCONV = -4,     /* some H-M sub-step stopped at max_iter without reaching tol */
+  MM_ENONFINITE = -5,  /* a sub-step residual was NaN or infinite */
+  MM_ESTATE = -6       /* call not allowed in the context's current state */
+} mm_status;
+
+typedef enum { MM_BC_PEC = 0, MM_BC_PERIODIC = 1 } mm_bc;         /* Sec. 3.2.3 */
+typedef enum { MM_FP64 = 0, MM_FP32 = 1 } mm_precision;
+
+/* Uniform Cartesian mesh (Sec. 3.1). */
+typedef struct {
+  int32_t nx, ny, nz;     /* cells per axis, each >= 1 */
+  int32_t bc[3];          /* mm_bc per axis */
+  double dx, dy, dz;      /* cell sizes (m) */
+} mm_grid;
+
+/* Material properties at cell centres (Sec. 3.1): host cell maps, copied by
+ * mm_init.  NULL selects the default in brackets.
+ *   eps_r  relative permittivity [1]          sigma  conductivity, S/m [0]
+ *   mu_r   relative permeability [1]          Ms     saturation magnetisation, A/m [0]
+ *   alpha  Gilbert damping [0]                gamma  gyromagnetic ratio, rad/(s T) [-1.759e11]
+ *   m0_dir 3 consecutive cell maps (x, y, z components) giving the direction
+ *          of the initial magnetisation; M0 = Ms * m0_dir at cell centres
+ *          [+z].  Faces take the mean of their two cells, renormalised to the
+ *          face Ms (Sec. 3.1).
+ * Edges take the mean of their 4 cells for eps and sigma; faces the mean of
+ * their 2 cells for Ms and mu (a PEC wall face uses its single cell); alpha
+ * and gamma on a face average the face's magnetic cells only.  A face is
+ * magnetic when its Ms is > 0 (Sec. 2, eq:Faraday2 / eq:Faraday3). */
+typedef struct {
+  const double *eps_r, *sigma, *mu_r, *Ms, *alpha, *gamma;
+  const double *m0_dir;
+} mm_materials;
+
+/* Uniform static bias H0 (A/m); it enters H_eff only (Sec. 2). */
+typedef struct { double H0[3]; } mm_bias;
+
+/* Soft current source J_src (Sec. 3.2, Step 2): J = profile * g(t) with
+ * g(t) = exp(-(t-t0)^2 / (2 Tp^2)) * cos(2 pi f0 t)  (pulse of Sec. 5.2.1),
+ * evaluated at t^{n+1/2}.  `profile` is a host array on component `comp`'s
+ * edge extent (A/m^2); entries on PEC walls are ignored. */
+typedef struct {
+  int32_t comp;           /* 0: Jx, 1: Jy, 2: Jz */
+  const double *profile;
+  double f0, Tp, t0;
+} mm_source;
+
+/* Options.  dev_alloc/dev_free, when both are set, supply all device memory
+ * of the context (e.g. a caching allocator); otherwise hipMalloc/hipFree. */
+typedef struct {
+  int32_t prec;           /* mm_precision.  MM_FP32: E, H and the cell maps are stored
+                             and updated in FP32; M, the LLG solve, the residual and
+                             the probe accumulators stay FP64 */
+  double tol;             /* sub-step stopping tolerance on max |dM|/Ms (Sec. 3.2.2), > 0 */
+  int32_t max_iter;       /* iteration cap per sub-step, >= 1 */
+  int32_t fixed_iter;     /* > 0: exactly this many iterations per sub-step (no test) */
+  void *hip_stream;       /* hipStream_t or NULL */
+  void *(*dev_alloc)(size_t bytes, void *ctx);
+  void (*dev_free)(void *ptr, void *ctx);
+  void *alloc_ctx;
+} mm_options;
+
+typedef struct mm_ctx mm_ctx;
+
+/* Create a context: validates the arguments (dt must not exceed the vacuum
+ * CFL limit 1/(c sqrt(1/dx^2+1/dy^2+1/dz^2))), copies every host input,
+ * builds the magnetic-face list and the edge/face material data, zeroes E
+ * and H and sets M to its initial value.  Host inputs may be freed on
+ * return.  src may be NULL.  Returns MM_EINVAL (with *out = NULL) on a bad
+ * argument. */
+mm_status mm_init(mm_ctx **out, const mm_grid *g, double dt, const mm_materials *mat,
+                  const mm_bias *bias, const mm_source *src, const mm_options *opt);
+
+/* Advance n >= 0 full time steps (Step 1, Step 2, Step 3 of Sec. 3.2.2,
+ * then probe sampling at level n+1).  Asynchronous on the context's stream. */
+mm_status mm_step(mm_ctx *c, int64_t n);
+
+/* Probes.  kind 0: sample field `field` (see below) at staggered index
+ * (i,j,k) after every step.  kind 1: Poynting flux through the node plane
+ * x = i, P = dy dz sum_{j,k} [Ey Hz - Ez Hy] with Hz, Hy averaged from the
+ * two cells beside the plane; i must be an interior node.  Field ids:
+ * 0-2 Ex,Ey,Ez; 3-5 Hx,Hy,Hz; 6+3f+c component c of M on the faces of
+ * family f; 15-17 normal B on x/y/z faces (mu0 (H + M_n) on magnetic faces,
+ * mu H elsewhere, Sec. 2).  Must be added before the first step. */
+typedef struct {
+  int32_t kind, field, i, j, k;
+} mm_probe_desc;
+
+mm_status mm_add_probe(mm_ctx *c, const mm_probe_desc *d, int32_t *id);
+
+/* Copy up to `cap` recorded values of probe `id` (one FP64 per step, oldest
+ * first) to host `out` (may be NULL to query); *n_written gets the number
+ * of recorded steps.  *sum (may be NULL) gets sum_n dt * value_n, the
+ * time-integrated value accumulated on the device in FP64 in step order.
+ * Synchronises the stream. */
+mm_status mm_probe(mm_ctx *c, int32_t id, double *out, size_t cap, size_t *n_written,
+                   double *sum);
+
+/* Copy field `field` (ids as for probes, 0-17) to the host array `dst` of
+ * doubles on its staggered extent (converted from FP32 in FP32 mode).
+ * Synchronises the stream. */
+mm_status mm_get_field(mm_ctx *c, int32_t field, double *dst);
+
+/* Overwrite E or H component `field` (0-5) from the host array `src` of
+ * doubles on its staggered extent; tangential E and normal H on PEC walls
+ * are forced to zero.  Allowed at any step boundary. */
+mm_status mm_set_field(mm_ctx *c, int32_t field, const double *src);
+
+/* Iteration counts of the sub-steps done so far (two per step, in order)
+ * into `iters` (up to cap; may be NULL); *n gets the total count.
+ * Synchronises the stream and returns the sticky device condition. */
+mm_status mm_stats(mm_ctx *c, int32_t *iters, size_t cap, size_t *n);
+
+/* Wait for the stream; returns the sticky device condition (MM_OK,
+ * MM_ENOCONV or MM_ENONFINITE) and clears it. */
+mm_status mm_sync(mm_ctx *c);
+
+/* Static description of the context: out[0..7] = number of evolving
+ * magnetic faces, magnetic faces on PEC walls, soft-source edges, padded x
+ * pitch, padded y rows, padded z planes, storage bytes per field element,
+ * device bytes held by the context. */
+mm_status mm_info(const mm_ctx *c, int64_t out[8]);
+
+/* Kernel timing.  mm_profile(c, 1) makes every later mm_step bracket each
+ * kernel launch with a pair of HIP events on the context's stream (class
+ * 0 e_update, 1 h_bulk, 2 hm_pre, 3 hm_iter, 4 add_source, 5 probes);
+ * mm_profile(c, 0) stops recording.  mm_profile_read synchronises, writes
+ * the summed elapsed milliseconds and the launch counts of each class to
+ * ms[0..7] / counts[0..7] (classes 6, 7 unused) and discards the records. */
+mm_status mm_profile(mm_ctx *c, int32_t enable);
+mm_status mm_profile_read(mm_ctx *c, double ms[8], int64_t counts[8]);
+
+/* Text of the last error recorded on this context ("" if none).  The
+ * pointer stays valid until the next call on the context. */
+const char *mm_last_error(const mm_ctx *c);
+
+/* Free the context and all its device memory (after waiting for the stream). */
+void mm_destroy(mm_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

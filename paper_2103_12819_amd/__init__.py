@@ -1,0 +1,236 @@
+"""MI355X coupled Maxwell-LLG time stepper: Python binding of libmm.so.
+
+The binding only marshals arguments to the C ABI of include/mm.h; every
+step of the computation runs in the HIP kernels of the library.  PyTorch
+supplies the device memory (through its caching allocator) and the stream.
+If the library has not been built, constructing a Sim raises: there is no
+CPU fallback.
+
+Scheme: Yao, Jambunathan, Zeng & Nonaka, "A Massively Parallel Time-Domain
+Coupled Electrodynamics-Micromagnetics Solver", Sec. 3.2.2.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _native as N
+
+FIELD_NAMES = ["Ex", "Ey", "Ez", "Hx", "Hy", "Hz",
+               "Mxx", "Mxy", "Mxz", "Myx", "Myy", "Myz", "Mzx", "Mzy", "Mzz",
+               "Bx", "By", "Bz"]
+FIELD_ID = {n: i for i, n in enumerate(FIELD_NAMES)}
+
+
+class MMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{N.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _dp(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _c64(a):
+    if a is None:
+        return None
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class _TorchAlloc:
+    """Device memory from torch's caching allocator on a given stream."""
+
+    def __init__(self, stream_ptr):
+        import torch
+        self.torch = torch
+        self.stream = int(stream_ptr or 0)
+        self.alloc_fn = N.ALLOC_FN(self._alloc)
+        self.free_fn = N.FREE_FN(self._free)
+
+    def _alloc(self, size, ctx):
+        try:
+            return int(self.torch.cuda.caching_allocator_alloc(int(size), stream=self.stream))
+        except Exception:  # allocation failure is reported by the library
+            return None
+
+    def _free(self, ptr, ctx):
+        if ptr:
+            self.torch.cuda.caching_allocator_delete(int(ptr))
+
+
+class Sim:
+    """One simulation context (mm_init ... mm_destroy).
+
+    Arguments follow mm_init: grid cells `n`, spacings `d`, time step `dt`,
+    cell maps in host layout (x fastest: numpy shape (nz, ny, nx)), bias
+    `H0`, optional source (comp, profile, f0, Tp, t0), periodic flags,
+    precision 'fp64' or 'fp32', tol, max_iter, fixed_iter.  `stream` is a
+    raw hipStream_t (int) or None for torch's current stream.
+    """
+
+    def __init__(self, n, d, dt, eps_r=None, sigma=None, mu_r=None, Ms=None, alpha=None,
+                 gamma=None, m0_dir=None, H0=(0.0, 0.0, 0.0), source=None,
+                 periodic=(False, False, False), precision="fp64", tol=1e-10, max_iter=100,
+                 fixed_iter=0, stream=None, torch_alloc=True):
+        self._lib = N.load()
+        self._ctx = C.c_void_p()
+        g = N.mm_grid(int(n[0]), int(n[1]), int(n[2]),
+                      (C.c_int32 * 3)(*[N.MM_BC_PERIODIC if p else N.MM_BC_PEC for p in periodic]),
+                      float(d[0]), float(d[1]), float(d[2]))
+        self.n = tuple(int(v) for v in n)
+        self.d = tuple(float(v) for v in d)
+        self.dt = float(dt)
+        self.periodic = tuple(bool(p) for p in periodic)
+        self._keep = [_c64(a) for a in (eps_r, sigma, mu_r, Ms, alpha, gamma, m0_dir)]
+        mat = N.mm_materials(*[_dp(a) for a in self._keep])
+        bias = N.mm_bias((C.c_double * 3)(*[float(v) for v in H0]))
+        src_p = None
+        if source is not None:
+            comp, prof, f0, Tp, t0 = source
+            self._prof = _c64(prof)
+            src_p = C.byref(N.mm_source(int(comp), _dp(self._prof), float(f0), float(Tp), float(t0)))
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else 0
+        self.stream = int(stream or 0)
+        opt = N.mm_options()
+        opt.prec = N.MM_FP32 if precision == "fp32" else N.MM_FP64
+        opt.tol = float(tol)
+        opt.max_iter = int(max_iter)
+        opt.fixed_iter = int(fixed_iter)
+        opt.hip_stream = self.stream or None
+        self._alloc = None
+        if torch_alloc:
+            self._alloc = _TorchAlloc(self.stream)
+            opt.dev_alloc = self._alloc.alloc_fn
+            opt.dev_free = self._alloc.free_fn
+        self.precision = precision
+        st = self._lib.mm_init(C.byref(self._ctx), C.byref(g), float(dt), C.byref(mat), C.byref(bias),
+                               src_p, C.byref(opt))
+        if st != 0:
+            raise MMError(st, "mm_init rejected the arguments")
+        self._keep = None
+        self._prof = None
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, st):
+        if st != 0:
+            msg = self._lib.mm_last_error(self._ctx)
+            raise MMError(st, msg.decode() if msg else "")
+
+    def nodes(self, ax):
+        return self.n[ax] if self.periodic[ax] else self.n[ax] + 1
+
+    def extent(self, field):
+        """Host-layout shape (nz', ny', nx') of a field id or name."""
+        fid = FIELD_ID[field] if isinstance(field, str) else int(field)
+        if fid < 3:
+            ext = [self.n[a] if a == fid else self.nodes(a) for a in range(3)]
+        else:
+            f = fid - 3 if fid < 6 else ((fid - 6) // 3 if fid < 15 else fid - 15)
+            ext = [self.nodes(a) if a == f else self.n[a] for a in range(3)]
+        return (ext[2], ext[1], ext[0])
+
+    # -- API -------------------------------------------------------------------
+    def add_probe(self, kind, field=0, i=0, j=0, k=0):
+        pid = C.c_int32()
+        self._check(self._lib.mm_add_probe(self._ctx, C.byref(N.mm_probe_desc(kind, field, i, j, k)),
+                                           C.byref(pid)))
+        return pid.value
+
+    def step(self, n=1):
+        self._check(self._lib.mm_step(self._ctx, int(n)))
+
+    def probe(self, pid):
+        """(series, time integral) of a probe; synchronises."""
+        cnt = C.c_size_t()
+        self._check(self._lib.mm_probe(self._ctx, int(pid), None, 0, C.byref(cnt), None))
+        out = np.zeros(cnt.value)
+        s = C.c_double()
+        self._check(self._lib.mm_probe(self._ctx, int(pid), _dp(out), out.size, C.byref(cnt), C.byref(s)))
+        return out, s.value
+
+    def field(self, name):
+        fid = FIELD_ID[name] if isinstance(name, str) else int(name)
+        out = np.zeros(self.extent(fid))
+        self._check(self._lib.mm_get_field(self._ctx, fid, _dp(out)))
+        return out
+
+    def set_field(self, name, arr):
+        fid = FIELD_ID[name] if isinstance(name, str) else int(name)
+        a = np.ascontiguousarray(arr, dtype=np.float64)
+        if a.shape != self.extent(fid):
+            raise ValueError(f"{name}: expected shape {self.extent(fid)}, got {a.shape}")
+        self._check(self._lib.mm_set_field(self._ctx, fid, _dp(a)))
+
+    def set_fields(self, E=None, H=None):
+        if E is not None:
+            for c in range(3):
+                self.set_field(c, E[c])
+        if H is not None:
+            for c in range(3):
+                self.set_field(3 + c, H[c])
+
+    def stats(self):
+        """Iteration counts of every sub-step so far (raises on a sticky device condition)."""
+        cnt = C.c_size_t()
+        self._check(self._lib.mm_stats(self._ctx, None, 0, C.byref(cnt)))
+        out = np.zeros(cnt.value, dtype=np.int32)
+        self._check(self._lib.mm_stats(self._ctx, out.ctypes.data_as(C.POINTER(C.c_int32)), out.size,
+                                       C.byref(cnt)))
+        return out
+
+    def sync(self):
+        self._check(self._lib.mm_sync(self._ctx))
+
+    def info(self):
+        out = (C.c_int64 * 8)()
+        self._check(self._lib.mm_info(self._ctx, out))
+        keys = ["n_mag", "n_wall_mag", "n_src", "px", "py", "pz", "elem_bytes", "device_bytes"]
+        return dict(zip(keys, list(out)))
+
+    KERNEL_CLASSES = ["e_update", "h_bulk", "hm_pre", "hm_iter", "add_source", "probes"]
+
+    def profile(self, enable=True):
+        """Bracket every later kernel launch with HIP events (see mm_profile)."""
+        self._check(self._lib.mm_profile(self._ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        """{class: (total ms, launches)} since the last read; synchronises."""
+        ms = (C.c_double * 8)()
+        cnt = (C.c_int64 * 8)()
+        self._check(self._lib.mm_profile_read(self._ctx, ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNEL_CLASSES)}
+
+    def close(self):
+        if self._ctx:
+            self._lib.mm_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def from_config(cfg, precision="fp64", fixed_iter=0, with_probes=True, **kw):
+    """Build a Sim from a workloads.Config (same inputs the oracle takes)."""
+    src = None
+    if cfg.source is not None:
+        s = cfg.source
+        src = (s.comp, s.profile, s.f0, s.Tp, s.t0)
+    sim = Sim(cfg.n, cfg.d, cfg.dt, eps_r=cfg.eps_r, sigma=cfg.sigma, mu_r=cfg.mu_r, Ms=cfg.Ms,
+              alpha=cfg.alpha, gamma=cfg.gamma, m0_dir=cfg.m0_dir, H0=cfg.H0, source=src,
+              periodic=cfg.periodic, precision=precision, tol=cfg.tol, max_iter=cfg.max_iter,
+              fixed_iter=fixed_iter, **kw)
+    if cfg.E_init is not None or cfg.H_init is not None:
+        sim.set_fields(cfg.E_init, cfg.H_init)
+    if with_probes:
+        for p in cfg.probes:
+            sim.add_probe(p.kind, p.field, p.i, p.j, p.k)
+    return sim

@@ -1,0 +1,1091 @@
+// Host runtime and C ABI of the coupled Maxwell-LLG stepper (see include/mm.h).
+//
+// mm_init turns the cell-centred inputs into the device layout (padded
+// field arrays, cell maps, the compact magnetic-face list with its
+// per-face constants, the soft-source edge list); mm_step enqueues the
+// kernel sequence of kernels.h on the context's stream; everything else is
+// argument checking, staging copies and probe/statistics bookkeeping.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mm.h"
+#include "kernels.h"
+
+using mmk::Geo;
+
+namespace {
+
+constexpr double kC0 = 299792458.0;
+
+struct ProbeRec {
+  mm_probe_desc d;
+  mmk::PointProbe pp;  // for kind 0
+};
+
+}  // namespace
+
+struct mm_ctx {
+  // geometry
+  int nx, ny, nz, per;
+  double dx, dy, dz, dt;
+  int px, py, pz;
+  size_t nelem;
+  int prec;
+  size_t esz;  // bytes per field element
+  double tol;
+  int max_iter, fixed_iter;
+  double H0[3];
+  hipStream_t stream;
+  void* (*ualloc)(size_t, void*);
+  void (*ufree)(void*, void*);
+  void* actx;
+  size_t dev_bytes;
+  std::vector<std::pair<void*, size_t>> allocs;
+  std::string err;
+  int sticky;  // host copy of the device error word (bits: 1 noconv, 2 nonfinite)
+
+  // fields and cell maps (T = double or float)
+  void* E[3];
+  void* H[3];
+  void* eps;
+  void* sig;
+  void* mu;
+
+  // magnetic faces
+  int nmag;     // evolving faces (families contiguous)
+  int nwall;    // magnetic faces on PEC walls (after the evolving ones; frozen)
+  int off1, off2;
+  std::vector<int> h_idx;  // all magnetic faces: padded index
+  std::vector<int> h_fam;
+  int* d_idx;
+  double *d_Ms, *d_kap, *d_aoms;
+  double* d_M[3];
+  double *d_b[3], *d_d[3], *d_q, *d_hnew;
+  unsigned long long* d_res;  // 2 * nres slots
+  int nres;
+  int coop_blocks;
+  int* d_err;
+
+  // iteration counts: one int per sub-step
+  int* d_iters;
+  size_t iters_cap;
+
+  // source: dense J0*p over the bounding box of its nonzero interior edges
+  int src_comp;
+  int nsrc;
+  int src_lo[3], src_hi[3];
+  double* d_src_prof;
+  double f0, Tp, t0;
+
+  // probes
+  std::vector<ProbeRec> probes;
+  size_t series_cap;
+  double* d_series;
+  double* d_sums;
+  mmk::PointProbe* d_points;
+  int npoints;
+  int* d_planes;
+  int* d_slots;
+  int nflux;
+  double* d_partial;
+  unsigned int* d_ticket;
+  int flux_blocks;
+  bool probes_frozen;
+
+  long step;
+  int substep;
+
+  // optional kernel timing (mm_profile)
+  bool prof;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  std::vector<int> ev_class;
+  size_t ev_used;
+};
+
+namespace {
+
+mm_status fail(mm_ctx* c, mm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return s;
+}
+
+#define HIPCHECK(ctx, call)                                                              \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, MM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));       \
+  } while (0)
+
+void* dalloc(mm_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  bytes = (bytes + 255) & ~size_t(255);
+  void* p = nullptr;
+  if (c->ualloc && c->ufree) {
+    p = c->ualloc(bytes, c->actx);
+  } else {
+    if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+  }
+  if (p) {
+    c->allocs.push_back({p, bytes});
+    c->dev_bytes += bytes;
+  }
+  return p;
+}
+
+void dfree(mm_ctx* c, void* p) {
+  if (!p) return;
+  for (size_t q = 0; q < c->allocs.size(); ++q) {
+    if (c->allocs[q].first == p) {
+      c->dev_bytes -= c->allocs[q].second;
+      c->allocs.erase(c->allocs.begin() + q);
+      break;
+    }
+  }
+  if (c->ualloc && c->ufree) c->ufree(p, c->actx);
+  else (void)hipFree(p);
+}
+
+inline size_t pidx(const mm_ctx* c, int i, int j, int k) {
+  return (size_t)i + (size_t)c->px * ((size_t)j + (size_t)c->py * (size_t)k);
+}
+
+inline int nodes(const mm_ctx* c, int ax) {
+  const int n = ax == 0 ? c->nx : (ax == 1 ? c->ny : c->nz);
+  return (c->per >> ax & 1) ? n : n + 1;
+}
+
+inline int ncell(const mm_ctx* c, int ax) { return ax == 0 ? c->nx : (ax == 1 ? c->ny : c->nz); }
+
+// staggered extent of field id 0..5 (E edges, H faces), and 6..17 (faces)
+void field_extent(const mm_ctx* c, int field, int ext[3]) {
+  if (field < 3) {
+    for (int a = 0; a < 3; ++a) ext[a] = (a == field) ? ncell(c, a) : nodes(c, a);
+  } else {
+    int f;
+    if (field < 6) f = field - 3;
+    else if (field < 15) f = (field - 6) / 3;
+    else f = field - 15;
+    for (int a = 0; a < 3; ++a) ext[a] = (a == f) ? nodes(c, a) : ncell(c, a);
+  }
+}
+
+// is staggered entry (i,j,k) of E/H component `field` (0..5) interior?
+bool entry_interior(const mm_ctx* c, int field, int i, int j, int k) {
+  const int p[3] = {i, j, k};
+  if (field < 3) {
+    for (int a = 0; a < 3; ++a) {
+      if (a == field || (c->per >> a & 1)) continue;
+      if (p[a] == 0 || p[a] == ncell(c, a)) return false;
+    }
+    return true;
+  }
+  const int f = field - 3;
+  if (c->per >> f & 1) return true;
+  return !(p[f] == 0 || p[f] == ncell(c, f));
+}
+
+double cell(const double* a, double def, const mm_ctx* c, int i, int j, int k) {
+  if (!a) return def;
+  return a[(size_t)i + (size_t)c->nx * ((size_t)j + (size_t)c->ny * (size_t)k)];
+}
+
+double waveform(double t, double f0, double Tp, double t0) {
+  return std::exp(-((t - t0) * (t - t0)) / (2.0 * Tp * Tp)) * std::cos(2.0 * M_PI * f0 * t);
+}
+
+template <typename T>
+mm_status upload_cellmap(mm_ctx* c, const double* src, double def, void** dst) {
+  std::vector<T> h(c->nelem, (T)0);
+  for (int k = 0; k < c->nz; ++k)
+    for (int j = 0; j < c->ny; ++j)
+      for (int i = 0; i < c->nx; ++i) h[pidx(c, i, j, k)] = (T)cell(src, def, c, i, j, k);
+  *dst = dalloc(c, c->nelem * sizeof(T));
+  if (!*dst) return fail(c, MM_ENOMEM, "device allocation of a cell map failed");
+  HIPCHECK(c, hipMemcpy(*dst, h.data(), c->nelem * sizeof(T), hipMemcpyHostToDevice));
+  return MM_OK;
+}
+
+mm_status grow_buffers(mm_ctx* c, size_t need_steps) {
+  // iteration counts (2 per step) and probe series
+  if (2 * need_steps > c->iters_cap) {
+    size_t cap = std::max<size_t>(2 * need_steps, 2 * c->iters_cap);
+    cap = std::max<size_t>(cap, 1024);
+    int* p = (int*)dalloc(c, cap * sizeof(int));
+    if (!p) return fail(c, MM_ENOMEM, "allocation of the iteration log failed");
+    if (c->d_iters && c->iters_cap)
+      HIPCHECK(c, hipMemcpyAsync(p, c->d_iters, c->iters_cap * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+    dfree(c, c->d_iters);
+    c->d_iters = p;
+    c->iters_cap = cap;
+  }
+  const size_t np = c->probes.size();
+  if (np && need_steps > c->series_cap) {
+    size_t cap = std::max<size_t>(need_steps, 2 * c->series_cap);
+    cap = std::max<size_t>(cap, 256);
+    double* p = (double*)dalloc(c, np * cap * sizeof(double));
+    if (!p) return fail(c, MM_ENOMEM, "allocation of the probe series failed");
+    if (c->d_series && c->series_cap)
+      HIPCHECK(c, hipMemcpy2DAsync(p, cap * sizeof(double), c->d_series, c->series_cap * sizeof(double),
+                                   c->series_cap * sizeof(double), np, hipMemcpyDeviceToDevice, c->stream));
+    dfree(c, c->d_series);
+    c->d_series = p;
+    c->series_cap = cap;
+    // the point descriptors do not depend on the capacity
+  }
+  return MM_OK;
+}
+
+mm_status freeze_probes(mm_ctx* c) {
+  if (c->probes_frozen) return MM_OK;
+  c->probes_frozen = true;
+  const size_t np = c->probes.size();
+  if (!np) return MM_OK;
+  std::vector<mmk::PointProbe> pts;
+  std::vector<int> planes, slots;
+  for (size_t s = 0; s < np; ++s) {
+    if (c->probes[s].d.kind == 0) {
+      mmk::PointProbe q = c->probes[s].pp;
+      q.slot = (int)s;
+      pts.push_back(q);
+    } else {
+      planes.push_back(c->probes[s].d.i);
+      slots.push_back((int)s);
+    }
+  }
+  c->npoints = (int)pts.size();
+  c->nflux = (int)planes.size();
+  c->d_sums = (double*)dalloc(c, np * sizeof(double));
+  if (!c->d_sums) return fail(c, MM_ENOMEM, "probe allocation failed");
+  HIPCHECK(c, hipMemsetAsync(c->d_sums, 0, np * sizeof(double), c->stream));
+  if (c->npoints) {
+    c->d_points = (mmk::PointProbe*)dalloc(c, pts.size() * sizeof(mmk::PointProbe));
+    if (!c->d_points) return fail(c, MM_ENOMEM, "probe allocation failed");
+    HIPCHECK(c, hipMemcpy(c->d_points, pts.data(), pts.size() * sizeof(mmk::PointProbe), hipMemcpyHostToDevice));
+  }
+  if (c->nflux) {
+    c->flux_blocks = 32;
+    c->d_planes = (int*)dalloc(c, planes.size() * sizeof(int));
+    c->d_slots = (int*)dalloc(c, slots.size() * sizeof(int));
+    c->d_partial = (double*)dalloc(c, (size_t)c->nflux * 2 * c->flux_blocks * sizeof(double));
+    c->d_ticket = (unsigned int*)dalloc(c, (size_t)c->nflux * sizeof(unsigned int));
+    if (!c->d_planes || !c->d_slots || !c->d_partial || !c->d_ticket)
+      return fail(c, MM_ENOMEM, "probe allocation failed");
+    HIPCHECK(c, hipMemcpy(c->d_planes, planes.data(), planes.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(c->d_slots, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemset(c->d_ticket, 0, (size_t)c->nflux * sizeof(unsigned int)));
+  }
+  return MM_OK;
+}
+
+// Bracket a launch with an event pair when profiling is on.
+struct Timed {
+  mm_ctx* c;
+  int cls;
+  hipEvent_t stop = nullptr;
+  Timed(mm_ctx* ctx, int k) : c(ctx), cls(k) {
+    if (!c->prof) return;
+    if (c->ev_used == c->ev_pool.size()) {
+      hipEvent_t a = nullptr, b = nullptr;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        c->prof = false;
+        return;
+      }
+      c->ev_pool.push_back({a, b});
+      c->ev_class.push_back(0);
+    }
+    c->ev_class[c->ev_used] = cls;
+    (void)hipEventRecord(c->ev_pool[c->ev_used].first, c->stream);
+    stop = c->ev_pool[c->ev_used].second;
+  }
+  ~Timed() {
+    if (!stop) return;
+    (void)hipEventRecord(stop, c->stream);
+    c->ev_used++;
+  }
+};
+
+Geo make_geo(const mm_ctx* c) {
+  Geo g;
+  g.nx = c->nx;
+  g.ny = c->ny;
+  g.nz = c->nz;
+  g.px = c->px;
+  g.sz = c->px * c->py;
+  g.per = c->per;
+  g.dx = c->dx;
+  g.dy = c->dy;
+  g.dz = c->dz;
+  g.idx = 1.0 / c->dx;
+  g.idy = 1.0 / c->dy;
+  g.idz = 1.0 / c->dz;
+  return g;
+}
+
+template <typename T>
+mmk::Fields<T> make_fields(const mm_ctx* c) {
+  mmk::Fields<T> F;
+  for (int a = 0; a < 3; ++a) {
+    F.E[a] = (T*)c->E[a];
+    F.H[a] = (T*)c->H[a];
+  }
+  return F;
+}
+
+mmk::Mag make_mag(const mm_ctx* c) {
+  mmk::Mag m;
+  m.idx = c->d_idx;
+  m.Ms = c->d_Ms;
+  m.kap = c->d_kap;
+  m.aoms = c->d_aoms;
+  for (int a = 0; a < 3; ++a) {
+    m.M[a] = c->d_M[a];
+    m.b[a] = c->d_b[a];
+    m.d[a] = c->d_d[a];
+  }
+  m.q = c->d_q;
+  m.hnew = c->d_hnew;
+  m.off1 = c->off1;
+  m.off2 = c->off2;
+  m.n = c->nmag;
+  return m;
+}
+
+int kchunk_for(const mm_ctx* c, dim3& grid) {
+  const int gx = (c->nx + 63) / 64, gy = (c->ny + 3) / 4;
+  // aim for >= ~4096 blocks while keeping each z run long enough to reuse
+  // the carried plane
+  int chunks = std::max(1, 4096 / std::max(1, gx * gy));
+  int kc = std::max(4, (c->nz + chunks - 1) / chunks);
+  kc = std::min(kc, c->nz);
+  grid = dim3(gx, gy, (c->nz + kc - 1) / kc);
+  return kc;
+}
+
+template <typename T>
+mm_status substep(mm_ctx* c) {
+  Geo g = make_geo(c);
+  mmk::Fields<T> F = make_fields<T>(c);
+  const double h = 0.5 * c->dt;
+  const double hmu0 = h / mmk::kMu0;
+  unsigned long long* res = c->d_res + (size_t)(c->substep & 1) * c->nres;
+  unsigned long long* res_next = c->d_res + (size_t)((c->substep + 1) & 1) * c->nres;
+  if (c->nmag > 0) {
+    mmk::Mag m = make_mag(c);
+    const int blocks = (c->nmag + 255) / 256;
+    Timed tm(c, 2);
+    hipLaunchKernelGGL((mmk::hm_pre<T>), dim3(blocks), dim3(256), 0, c->stream, g, F, m, hmu0, c->H0[0],
+                       c->H0[1], c->H0[2], res + 1);
+    HIPCHECK(c, hipGetLastError());
+  }
+  dim3 grid;
+  const int kc = kchunk_for(c, grid);
+  {
+  Timed tm(c, 1);
+  if (c->mu)
+    hipLaunchKernelGGL((mmk::h_bulk<T, true>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->H[0], (T*)c->H[1],
+                       (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2], (const T*)c->mu,
+                       (T)hmu0, (T)h, kc);
+  else
+    hipLaunchKernelGGL((mmk::h_bulk<T, false>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->H[0], (T*)c->H[1],
+                       (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2], (const T*)c->mu,
+                       (T)hmu0, (T)h, kc);
+  }
+  HIPCHECK(c, hipGetLastError());
+  if (c->nmag > 0) {
+    mmk::Mag m = make_mag(c);
+    double H0x = c->H0[0], H0y = c->H0[1], H0z = c->H0[2];
+    int nres = c->nres;
+    double tol = c->tol;
+    int max_iter = c->max_iter, fixed_iter = c->fixed_iter;
+    int* iters_out = c->d_iters + c->substep;
+    int* err = c->d_err;
+    void* args[] = {(void*)&g,   (void*)&F,        (void*)&m,    (void*)&H0x,      (void*)&H0y,
+                    (void*)&H0z, (void*)&res,      (void*)&res_next, (void*)&nres, (void*)&tol,
+                    (void*)&max_iter, (void*)&fixed_iter, (void*)&iters_out, (void*)&err};
+    Timed tm(c, 3);
+    HIPCHECK(c, hipLaunchCooperativeKernel((const void*)&mmk::hm_iter<T>, dim3(c->coop_blocks), dim3(256), args,
+                                           0, c->stream));
+  }
+  c->substep++;
+  return MM_OK;
+}
+
+template <typename T>
+mm_status one_step(mm_ctx* c) {
+  mm_status s = substep<T>(c);  // Step 1
+  if (s) return s;
+  const Geo g = make_geo(c);
+  dim3 grid;
+  const int kc = kchunk_for(c, grid);
+  mmk::Src src;
+  std::memset(&src, 0, sizeof src);
+  src.comp = -1;
+  if (c->nsrc > 0) {
+    src.prof = c->d_src_prof;
+    src.comp = c->src_comp;
+    for (int a = 0; a < 3; ++a) {
+      src.lo[a] = c->src_lo[a];
+      src.hi[a] = c->src_hi[a];
+    }
+    src.g = waveform(((double)c->step + 0.5) * c->dt, c->f0, c->Tp, c->t0);
+  }
+  {
+    Timed tm(c, 0);
+    if (c->sig)
+      hipLaunchKernelGGL((mmk::e_update<T, true>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->E[0], (T*)c->E[1],
+                         (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], (const T*)c->eps,
+                         (const T*)c->sig, (T)c->dt, src, kc);
+    else
+      hipLaunchKernelGGL((mmk::e_update<T, false>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->E[0], (T*)c->E[1],
+                         (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], (const T*)c->eps,
+                         (const T*)c->sig, (T)c->dt, src, kc);
+  }
+  HIPCHECK(c, hipGetLastError());
+  s = substep<T>(c);  // Step 3
+  if (s) return s;
+  // probes at level n+1
+  Timed tm(c, 5);
+  if (c->npoints)
+    hipLaunchKernelGGL((mmk::probe_points<T>), dim3((c->npoints + 63) / 64), dim3(64), 0, c->stream, c->d_points,
+                       c->npoints, c->d_series, c->series_cap, c->d_sums, c->step, c->dt);
+  if (c->nflux) {
+    const int NY = nodes(c, 1), NZ = nodes(c, 2);
+    hipLaunchKernelGGL((mmk::probe_flux<T>), dim3(c->flux_blocks, c->nflux), dim3(256), 0, c->stream, g,
+                       make_fields<T>(c), c->d_planes, c->d_slots, c->d_partial, c->d_ticket, c->d_series,
+                       c->series_cap, c->d_sums, c->step, c->dt, c->dy * c->dz, NY, NZ);
+  }
+  HIPCHECK(c, hipGetLastError());
+  c->step++;
+  return MM_OK;
+}
+
+mm_status read_sticky(mm_ctx* c) {
+  int w = 0;
+  HIPCHECK(c, hipMemcpy(&w, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  if (w) {
+    c->sticky |= w;
+    HIPCHECK(c, hipMemset(c->d_err, 0, sizeof(int)));
+  }
+  return MM_OK;
+}
+
+mm_status take_sticky(mm_ctx* c) {
+  const int w = c->sticky;
+  c->sticky = 0;
+  if (w & 2) return fail(c, MM_ENONFINITE, "a sub-step residual was not finite");
+  if (w & 1) return fail(c, MM_ENOCONV, "a sub-step reached max_iter without meeting tol");
+  return MM_OK;
+}
+
+bool finite_nonneg(const double* a, size_t n, bool strictly_positive) {
+  if (!a) return true;
+  for (size_t q = 0; q < n; ++q) {
+    if (!std::isfinite(a[q])) return false;
+    if (strictly_positive ? !(a[q] > 0) : !(a[q] >= 0)) return false;
+  }
+  return true;
+}
+
+mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
+  const size_t ncells = (size_t)c->nx * c->ny * c->nz;
+  const bool fp32 = c->prec == MM_FP32;
+  // fields
+  for (int a = 0; a < 3; ++a) {
+    c->E[a] = dalloc(c, c->nelem * c->esz);
+    c->H[a] = dalloc(c, c->nelem * c->esz);
+    if (!c->E[a] || !c->H[a]) return fail(c, MM_ENOMEM, "device allocation of the fields failed");
+    HIPCHECK(c, hipMemsetAsync(c->E[a], 0, c->nelem * c->esz, c->stream));
+    HIPCHECK(c, hipMemsetAsync(c->H[a], 0, c->nelem * c->esz, c->stream));
+  }
+  // cell maps: eps always; sigma only if some cell conducts; mu only if some mu_r != 1
+  bool any_sig = false, any_mu = false;
+  if (mat->sigma)
+    for (size_t q = 0; q < ncells && !any_sig; ++q) any_sig = mat->sigma[q] != 0.0;
+  if (mat->mu_r)
+    for (size_t q = 0; q < ncells && !any_mu; ++q) any_mu = mat->mu_r[q] != 1.0;
+  mm_status s;
+  s = fp32 ? upload_cellmap<float>(c, mat->eps_r, 1.0, &c->eps) : upload_cellmap<double>(c, mat->eps_r, 1.0, &c->eps);
+  if (s) return s;
+  if (any_sig) {
+    s = fp32 ? upload_cellmap<float>(c, mat->sigma, 0.0, &c->sig) : upload_cellmap<double>(c, mat->sigma, 0.0, &c->sig);
+    if (s) return s;
+  }
+  if (any_mu) {
+    s = fp32 ? upload_cellmap<float>(c, mat->mu_r, 1.0, &c->mu) : upload_cellmap<double>(c, mat->mu_r, 1.0, &c->mu);
+    if (s) return s;
+  }
+
+  // magnetic faces: Ms_f = mean of the 2 cells (a PEC wall face uses its one
+  // cell); alpha_f, gamma_f over the magnetic cells only; M0_f = mean of
+  // Ms*m0_dir renormalised to Ms_f (Sec. 3.1).
+  std::vector<int> ev_idx[3], wl_idx[3];
+  std::vector<double> ev_v[3][7], wl_v[3][7];  // Ms, kap, aoms, M0x, M0y, M0z, unused
+  for (int f = 0; f < 3; ++f) {
+    int ext[3];
+    field_extent(c, 3 + f, ext);
+    const bool pf = c->per >> f & 1;
+    const int nf = ncell(c, f);
+    for (int k = 0; k < ext[2]; ++k)
+      for (int j = 0; j < ext[1]; ++j)
+        for (int i = 0; i < ext[0]; ++i) {
+          int p[3] = {i, j, k};
+          int qa[3] = {i, j, k}, qb[3] = {i, j, k};
+          bool wall = false;
+          // the two cells sharing the face: index-1 and index along f
+          qa[f] = p[f] - 1;
+          qb[f] = p[f];
+          if (pf) {
+            if (qa[f] < 0) qa[f] = nf - 1;
+          } else {
+            if (p[f] == 0) { qa[f] = 0; wall = true; }
+            if (p[f] == nf) { qb[f] = nf - 1; wall = true; }
+          }
+          const double msa = cell(mat->Ms, 0.0, c, qa[0], qa[1], qa[2]);
+          const double msb = cell(mat->Ms, 0.0, c, qb[0], qb[1], qb[2]);
+          double Msf;
+          if (wall) {
+            const double v = (p[f] == 0) ? msb : msa;
+            Msf = 0.5 * (2.0 * v);
+          } else {
+            Msf = 0.5 * (msa + msb);
+          }
+          if (!(Msf > 0)) continue;
+          const double ma = msa > 0 ? 1.0 : 0.0, mb = msb > 0 ? 1.0 : 0.0;
+          const double aa = cell(mat->alpha, 0.0, c, qa[0], qa[1], qa[2]);
+          const double ab = cell(mat->alpha, 0.0, c, qb[0], qb[1], qb[2]);
+          const double ga = cell(mat->gamma, -1.759e11, c, qa[0], qa[1], qa[2]);
+          const double gb = cell(mat->gamma, -1.759e11, c, qb[0], qb[1], qb[2]);
+          double af, gf, M0[3];
+          const size_t ncell_all = ncells;
+          auto mdir = [&](int comp, const int q[3]) {
+            if (!mat->m0_dir) return comp == 2 ? 1.0 : 0.0;
+            return mat->m0_dir[(size_t)comp * ncell_all + (size_t)q[0] + (size_t)c->nx * ((size_t)q[1] + (size_t)c->ny * (size_t)q[2])];
+          };
+          if (wall) {
+            const int* q = (p[f] == 0) ? qb : qa;
+            const double m = (p[f] == 0) ? mb : ma;
+            const double al = (p[f] == 0) ? ab : aa;
+            const double ga1 = (p[f] == 0) ? gb : ga;
+            const double ms = (p[f] == 0) ? msb : msa;
+            af = (2.0 * al * m) / (2.0 * m);
+            gf = (2.0 * ga1 * m) / (2.0 * m);
+            for (int cc = 0; cc < 3; ++cc) M0[cc] = 0.5 * (2.0 * (ms * mdir(cc, q)));
+          } else {
+            const double cnt = ma + mb;
+            af = (aa * ma + ab * mb) / cnt;
+            gf = (ga * ma + gb * mb) / cnt;
+            for (int cc = 0; cc < 3; ++cc) M0[cc] = 0.5 * (msa * mdir(cc, qa) + msb * mdir(cc, qb));
+          }
+          const double nrm = std::sqrt((M0[0] * M0[0] + M0[1] * M0[1]) + M0[2] * M0[2]);
+          if (!(nrm > 0)) return fail(c, MM_EINVAL, "initial magnetisation averages to zero on a magnetic face");
+          const double sc = Msf / nrm;
+          const double kap = mmk::kMu0 * gf * c->dt / 4.0;
+          const double vals[7] = {Msf, kap, af / Msf, M0[0] * sc, M0[1] * sc, M0[2] * sc, 0.0};
+          const int pi = (int)pidx(c, i, j, k);
+          if (wall) {
+            wl_idx[f].push_back(pi);
+            for (int v = 0; v < 7; ++v) wl_v[f][v].push_back(vals[v]);
+          } else {
+            ev_idx[f].push_back(pi);
+            for (int v = 0; v < 7; ++v) ev_v[f][v].push_back(vals[v]);
+          }
+        }
+  }
+  c->off1 = (int)ev_idx[0].size();
+  c->off2 = c->off1 + (int)ev_idx[1].size();
+  c->nmag = c->off2 + (int)ev_idx[2].size();
+  c->nwall = (int)(wl_idx[0].size() + wl_idx[1].size() + wl_idx[2].size());
+  const size_t ntot = (size_t)c->nmag + c->nwall;
+  std::vector<double> hv[7];
+  c->h_idx.clear();
+  c->h_fam.clear();
+  for (int f = 0; f < 3; ++f) {
+    c->h_idx.insert(c->h_idx.end(), ev_idx[f].begin(), ev_idx[f].end());
+    c->h_fam.insert(c->h_fam.end(), ev_idx[f].size(), f);
+    for (int v = 0; v < 7; ++v) hv[v].insert(hv[v].end(), ev_v[f][v].begin(), ev_v[f][v].end());
+  }
+  for (int f = 0; f < 3; ++f) {
+    c->h_idx.insert(c->h_idx.end(), wl_idx[f].begin(), wl_idx[f].end());
+    c->h_fam.insert(c->h_fam.end(), wl_idx[f].size(), f);
+    for (int v = 0; v < 7; ++v) hv[v].insert(hv[v].end(), wl_v[f][v].begin(), wl_v[f][v].end());
+  }
+  if (ntot > 0) {
+    c->d_idx = (int*)dalloc(c, ntot * sizeof(int));
+    c->d_Ms = (double*)dalloc(c, ntot * sizeof(double));
+    c->d_kap = (double*)dalloc(c, ntot * sizeof(double));
+    c->d_aoms = (double*)dalloc(c, ntot * sizeof(double));
+    for (int a = 0; a < 3; ++a) {
+      c->d_M[a] = (double*)dalloc(c, ntot * sizeof(double));
+      c->d_b[a] = (double*)dalloc(c, ntot * sizeof(double));
+      c->d_d[a] = (double*)dalloc(c, ntot * sizeof(double));
+      if (!c->d_M[a] || !c->d_b[a] || !c->d_d[a]) return fail(c, MM_ENOMEM, "magnetic-face allocation failed");
+    }
+    c->d_q = (double*)dalloc(c, ntot * sizeof(double));
+    c->d_hnew = (double*)dalloc(c, ntot * sizeof(double));
+    if (!c->d_idx || !c->d_Ms || !c->d_kap || !c->d_aoms || !c->d_q || !c->d_hnew)
+      return fail(c, MM_ENOMEM, "magnetic-face allocation failed");
+    HIPCHECK(c, hipMemcpy(c->d_idx, c->h_idx.data(), ntot * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(c->d_Ms, hv[0].data(), ntot * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(c->d_kap, hv[1].data(), ntot * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(c->d_aoms, hv[2].data(), ntot * sizeof(double), hipMemcpyHostToDevice));
+    for (int a = 0; a < 3; ++a)
+      HIPCHECK(c, hipMemcpy(c->d_M[a], hv[3 + a].data(), ntot * sizeof(double), hipMemcpyHostToDevice));
+  }
+  c->nres = std::max(c->max_iter, c->fixed_iter) + 1;
+  c->d_res = (unsigned long long*)dalloc(c, 2 * (size_t)c->nres * sizeof(unsigned long long));
+  c->d_err = (int*)dalloc(c, sizeof(int));
+  if (!c->d_res || !c->d_err) return fail(c, MM_ENOMEM, "allocation failed");
+  HIPCHECK(c, hipMemset(c->d_res, 0, 2 * (size_t)c->nres * sizeof(unsigned long long)));
+  HIPCHECK(c, hipMemset(c->d_err, 0, sizeof(int)));
+  if (c->nmag > 0) {
+    int per_cu = 0;
+    HIPCHECK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, fp32 ? (const void*)&mmk::hm_iter<float> : (const void*)&mmk::hm_iter<double>, 256, 0));
+    int dev = 0, ncu = 0;
+    HIPCHECK(c, hipGetDevice(&dev));
+    HIPCHECK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int want = (c->nmag + 255) / 256;
+    c->coop_blocks = std::max(1, std::min(want, per_cu * ncu));
+    if (per_cu < 1) return fail(c, MM_EDEVICE, "the iteration kernel cannot be made resident");
+  }
+
+  // soft source: J0 p over the bounding box of its nonzero interior edges
+  c->nsrc = 0;
+  if (src && src->profile) {
+    const int cp = src->comp;
+    int ext[3];
+    field_extent(c, cp, ext);
+    int lo[3] = {ext[0], ext[1], ext[2]}, hi[3] = {0, 0, 0};
+    auto prof_at = [&](int i, int j, int k) {
+      return src->profile[(size_t)i + (size_t)ext[0] * ((size_t)j + (size_t)ext[1] * k)];
+    };
+    for (int k = 0; k < ext[2]; ++k)
+      for (int j = 0; j < ext[1]; ++j)
+        for (int i = 0; i < ext[0]; ++i) {
+          if (prof_at(i, j, k) == 0.0 || !entry_interior(c, cp, i, j, k)) continue;
+          c->nsrc++;
+          const int p[3] = {i, j, k};
+          for (int a2 = 0; a2 < 3; ++a2) {
+            lo[a2] = std::min(lo[a2], p[a2]);
+            hi[a2] = std::max(hi[a2], p[a2] + 1);
+          }
+        }
+    if (c->nsrc) {
+      const size_t bx = hi[0] - lo[0], by = hi[1] - lo[1], bz = hi[2] - lo[2];
+      std::vector<double> box(bx * by * bz, 0.0);
+      for (size_t k = 0; k < bz; ++k)
+        for (size_t j = 0; j < by; ++j)
+          for (size_t i = 0; i < bx; ++i) {
+            const int gi = lo[0] + (int)i, gj = lo[1] + (int)j, gk = lo[2] + (int)k;
+            if (entry_interior(c, cp, gi, gj, gk)) box[i + bx * (j + by * k)] = prof_at(gi, gj, gk);
+          }
+      c->d_src_prof = (double*)dalloc(c, box.size() * sizeof(double));
+      if (!c->d_src_prof) return fail(c, MM_ENOMEM, "source allocation failed");
+      HIPCHECK(c, hipMemcpy(c->d_src_prof, box.data(), box.size() * sizeof(double), hipMemcpyHostToDevice));
+      for (int a2 = 0; a2 < 3; ++a2) {
+        c->src_lo[a2] = lo[a2];
+        c->src_hi[a2] = hi[a2];
+      }
+    }
+    c->src_comp = cp;
+    c->f0 = src->f0;
+    c->Tp = src->Tp;
+    c->t0 = src->t0;
+  }
+  return MM_OK;
+}
+
+void release(mm_ctx* c) {
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  for (auto& pr : c->ev_pool) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  c->ev_pool.clear();
+  while (!c->allocs.empty()) dfree(c, c->allocs.back().first);
+}
+
+}  // namespace
+
+extern "C" {
+
+mm_status mm_init(mm_ctx** out, const mm_grid* g, double dt, const mm_materials* mat, const mm_bias* bias,
+                  const mm_source* src, const mm_options* opt) {
+  if (!out) return MM_EINVAL;
+  *out = nullptr;
+  if (!g || !mat || !opt) return MM_EINVAL;
+  mm_ctx* c = new mm_ctx();
+  auto bad = [&](const char* msg) {
+    delete c;
+    (void)msg;
+    return MM_EINVAL;
+  };
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return bad("grid");
+  for (int a = 0; a < 3; ++a)
+    if (g->bc[a] != MM_BC_PEC && g->bc[a] != MM_BC_PERIODIC) return bad("bc");
+  if (!(g->dx > 0) || !(g->dy > 0) || !(g->dz > 0) || !std::isfinite(g->dx + g->dy + g->dz)) return bad("spacing");
+  const double dtmax = 1.0 / (kC0 * std::sqrt(1.0 / (g->dx * g->dx) + 1.0 / (g->dy * g->dy) + 1.0 / (g->dz * g->dz)));
+  if (!(dt > 0) || !(dt <= dtmax * (1.0 + 1e-12))) return bad("dt");
+  if (!(opt->tol > 0) || opt->max_iter < 1 || opt->fixed_iter < 0 || opt->fixed_iter > 1000000 ||
+      opt->max_iter > 1000000)
+    return bad("iteration options");
+  if (opt->prec != MM_FP64 && opt->prec != MM_FP32) return bad("precision");
+  const size_t ncells = (size_t)g->nx * g->ny * g->nz;
+  if (!finite_nonneg(mat->eps_r, ncells, true) || !finite_nonneg(mat->mu_r, ncells, true) ||
+      !finite_nonneg(mat->sigma, ncells, false) || !finite_nonneg(mat->Ms, ncells, false) ||
+      !finite_nonneg(mat->alpha, ncells, false))
+    return bad("material map");
+  if (mat->gamma)
+    for (size_t q = 0; q < ncells; ++q)
+      if (!std::isfinite(mat->gamma[q])) return bad("gamma");
+  if (mat->m0_dir)
+    for (size_t q = 0; q < 3 * ncells; ++q)
+      if (!std::isfinite(mat->m0_dir[q])) return bad("m0_dir");
+  if (src && src->profile) {
+    if (src->comp < 0 || src->comp > 2 || !(src->Tp > 0) || !std::isfinite(src->f0) || !std::isfinite(src->t0))
+      return bad("source");
+  }
+  c->nx = g->nx;
+  c->ny = g->ny;
+  c->nz = g->nz;
+  c->per = (g->bc[0] == MM_BC_PERIODIC ? 1 : 0) | (g->bc[1] == MM_BC_PERIODIC ? 2 : 0) |
+           (g->bc[2] == MM_BC_PERIODIC ? 4 : 0);
+  c->dx = g->dx;
+  c->dy = g->dy;
+  c->dz = g->dz;
+  c->dt = dt;
+  c->px = ((c->nx + 1) + 31) / 32 * 32;
+  c->py = c->ny + 1;
+  c->pz = c->nz + 1;
+  const double ne = (double)c->px * c->py * c->pz;
+  if (ne >= 2147483647.0) return bad("grid too large for 32-bit indexing");
+  c->nelem = (size_t)c->px * c->py * c->pz;
+  c->prec = opt->prec;
+  c->esz = opt->prec == MM_FP32 ? 4 : 8;
+  c->tol = opt->tol;
+  c->max_iter = opt->max_iter;
+  c->fixed_iter = opt->fixed_iter;
+  for (int a = 0; a < 3; ++a) c->H0[a] = bias ? bias->H0[a] : 0.0;
+  c->stream = (hipStream_t)opt->hip_stream;
+  c->ualloc = opt->dev_alloc;
+  c->ufree = opt->dev_free;
+  c->actx = opt->alloc_ctx;
+  mm_status s = build(c, mat, src);
+  if (s == MM_OK) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) s = fail(c, MM_EDEVICE, "init: %s", hipGetErrorString(e));
+  }
+  if (s != MM_OK) {
+    std::fprintf(stderr, "mm_init: %s\n", c->err.c_str());
+    release(c);
+    delete c;
+    return s;
+  }
+  *out = c;
+  return MM_OK;
+}
+
+mm_status mm_step(mm_ctx* c, int64_t n) {
+  if (!c) return MM_EINVAL;
+  if (n < 0) return fail(c, MM_EINVAL, "negative step count");
+  if (n == 0) return MM_OK;
+  mm_status s = freeze_probes(c);
+  if (s) return s;
+  s = grow_buffers(c, (size_t)(c->step + n));
+  if (s) return s;
+  for (int64_t q = 0; q < n; ++q) {
+    s = c->prec == MM_FP32 ? one_step<float>(c) : one_step<double>(c);
+    if (s) return s;
+  }
+  return MM_OK;
+}
+
+mm_status mm_add_probe(mm_ctx* c, const mm_probe_desc* d, int32_t* id) {
+  if (!c || !d) return MM_EINVAL;
+  if (c->step > 0 || c->probes_frozen) return fail(c, MM_ESTATE, "probes must be added before the first step");
+  ProbeRec r;
+  r.d = *d;
+  std::memset(&r.pp, 0, sizeof r.pp);
+  if (d->kind == 1) {
+    const bool pxp = c->per & 1;
+    if (pxp ? (d->i < 0 || d->i >= c->nx) : (d->i < 1 || d->i >= c->nx))
+      return fail(c, MM_EINVAL, "flux plane must be an interior x node");
+  } else if (d->kind == 0) {
+    if (d->field < 0 || d->field > 17) return fail(c, MM_EINVAL, "bad probe field");
+    int ext[3];
+    field_extent(c, d->field, ext);
+    if (d->i < 0 || d->j < 0 || d->k < 0 || d->i >= ext[0] || d->j >= ext[1] || d->k >= ext[2])
+      return fail(c, MM_EINVAL, "probe index outside the field extent");
+    const int pi = (int)pidx(c, d->i, d->j, d->k);
+    if (d->field < 6) {
+      r.pp.h = d->field < 3 ? c->E[d->field] : c->H[d->field - 3];
+      r.pp.ih = pi;
+      r.pp.ch = 1.0;
+    } else {
+      const int f = d->field < 15 ? (d->field - 6) / 3 : d->field - 15;
+      int m = -1;
+      for (size_t q = 0; q < c->h_idx.size(); ++q)
+        if (c->h_fam[q] == f && c->h_idx[q] == pi) { m = (int)q; break; }
+      if (d->field < 15) {
+        const int comp = (d->field - 6) % 3;
+        if (m >= 0) {
+          r.pp.mcomp = c->d_M[comp];
+          r.pp.im = m;
+          r.pp.cm = 1.0;
+        }
+      } else {
+        r.pp.h = c->H[f];
+        r.pp.ih = pi;
+        if (m >= 0) {
+          r.pp.ch = mmk::kMu0;
+          r.pp.mcomp = c->d_M[f];
+          r.pp.im = m;
+          r.pp.cm = mmk::kMu0;
+        } else {
+          // mu_f from the two cells beside the face (clamped at PEC walls)
+          double mu = 1.0;
+          if (c->mu) {
+            std::vector<double> tmp(c->nelem);
+            if (c->esz == 8) {
+              HIPCHECK(c, hipMemcpy(tmp.data(), c->mu, c->nelem * 8, hipMemcpyDeviceToHost));
+            } else {
+              std::vector<float> tf(c->nelem);
+              HIPCHECK(c, hipMemcpy(tf.data(), c->mu, c->nelem * 4, hipMemcpyDeviceToHost));
+              for (size_t q = 0; q < c->nelem; ++q) tmp[q] = tf[q];
+            }
+            int qa[3] = {d->i, d->j, d->k}, qb[3] = {d->i, d->j, d->k};
+            qa[f] -= 1;
+            const int nf = ncell(c, f);
+            if (qa[f] < 0) qa[f] = (c->per >> f & 1) ? nf - 1 : 0;
+            if (qb[f] >= nf) qb[f] = nf - 1;
+            mu = 0.5 * (tmp[pidx(c, qa[0], qa[1], qa[2])] + tmp[pidx(c, qb[0], qb[1], qb[2])]);
+          }
+          r.pp.ch = mmk::kMu0 * mu;
+        }
+      }
+    }
+  } else {
+    return fail(c, MM_EINVAL, "bad probe kind");
+  }
+  c->probes.push_back(r);
+  if (id) *id = (int32_t)(c->probes.size() - 1);
+  return MM_OK;
+}
+
+mm_status mm_probe(mm_ctx* c, int32_t id, double* out, size_t cap, size_t* n_written, double* sum) {
+  if (!c) return MM_EINVAL;
+  if (id < 0 || (size_t)id >= c->probes.size()) return fail(c, MM_EINVAL, "bad probe id");
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  const size_t n = (size_t)c->step;
+  if (n_written) *n_written = n;
+  if (out && n && c->d_series) {
+    const size_t m = std::min(cap, n);
+    HIPCHECK(c, hipMemcpy(out, c->d_series + (size_t)id * c->series_cap, m * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  if (sum) {
+    *sum = 0.0;
+    if (c->d_sums) HIPCHECK(c, hipMemcpy(sum, c->d_sums + id, sizeof(double), hipMemcpyDeviceToHost));
+  }
+  mm_status s = read_sticky(c);
+  if (s) return s;
+  return take_sticky(c);
+}
+
+mm_status mm_get_field(mm_ctx* c, int32_t field, double* dst) {
+  if (!c || !dst) return MM_EINVAL;
+  if (field < 0 || field > 17) return fail(c, MM_EINVAL, "bad field id");
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  int ext[3];
+  field_extent(c, field, ext);
+  const size_t n = (size_t)ext[0] * ext[1] * ext[2];
+  std::fill(dst, dst + n, 0.0);
+  auto out_at = [&](int i, int j, int k) -> double& {
+    return dst[(size_t)i + (size_t)ext[0] * ((size_t)j + (size_t)ext[1] * k)];
+  };
+  std::vector<double> fld;
+  auto fetch = [&](void* p) -> mm_status {
+    fld.assign(c->nelem, 0.0);
+    if (c->esz == 8) {
+      HIPCHECK(c, hipMemcpy(fld.data(), p, c->nelem * 8, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> tf(c->nelem);
+      HIPCHECK(c, hipMemcpy(tf.data(), p, c->nelem * 4, hipMemcpyDeviceToHost));
+      for (size_t q = 0; q < c->nelem; ++q) fld[q] = tf[q];
+    }
+    return MM_OK;
+  };
+  const size_t ntot = c->h_idx.size();
+  std::vector<double> mc;
+  auto fetch_m = [&](int comp) -> mm_status {
+    mc.assign(ntot, 0.0);
+    if (ntot) HIPCHECK(c, hipMemcpy(mc.data(), c->d_M[comp], ntot * sizeof(double), hipMemcpyDeviceToHost));
+    return MM_OK;
+  };
+  mm_status s;
+  if (field < 6) {
+    s = fetch(field < 3 ? c->E[field] : c->H[field - 3]);
+    if (s) return s;
+    for (int k = 0; k < ext[2]; ++k)
+      for (int j = 0; j < ext[1]; ++j)
+        for (int i = 0; i < ext[0]; ++i) out_at(i, j, k) = fld[pidx(c, i, j, k)];
+  } else if (field < 15) {
+    const int f = (field - 6) / 3, comp = (field - 6) % 3;
+    s = fetch_m(comp);
+    if (s) return s;
+    for (size_t q = 0; q < ntot; ++q) {
+      if (c->h_fam[q] != f) continue;
+      const int pi = c->h_idx[q];
+      const int k = pi / (c->px * c->py), r = pi - k * c->px * c->py, j = r / c->px, i = r - j * c->px;
+      out_at(i, j, k) = mc[q];
+    }
+  } else {
+    const int f = field - 15;
+    s = fetch(c->H[f]);
+    if (s) return s;
+    std::vector<double> mu;
+    if (c->mu) {
+      std::vector<double> keep = fld;
+      s = fetch(c->mu);
+      if (s) return s;
+      mu = fld;
+      fld = keep;
+    }
+    const int nf = ncell(c, f);
+    for (int k = 0; k < ext[2]; ++k)
+      for (int j = 0; j < ext[1]; ++j)
+        for (int i = 0; i < ext[0]; ++i) {
+          double muf = 1.0;
+          if (c->mu) {
+            int qa[3] = {i, j, k}, qb[3] = {i, j, k};
+            qa[f] -= 1;
+            if (qa[f] < 0) qa[f] = (c->per >> f & 1) ? nf - 1 : 0;
+            if (qb[f] >= nf) qb[f] = nf - 1;
+            muf = 0.5 * (mu[pidx(c, qa[0], qa[1], qa[2])] + mu[pidx(c, qb[0], qb[1], qb[2])]);
+          }
+          out_at(i, j, k) = mmk::kMu0 * muf * fld[pidx(c, i, j, k)];
+        }
+    s = fetch_m(f);
+    if (s) return s;
+    for (size_t q = 0; q < ntot; ++q) {
+      if (c->h_fam[q] != f) continue;
+      const int pi = c->h_idx[q];
+      const int k = pi / (c->px * c->py), r = pi - k * c->px * c->py, j = r / c->px, i = r - j * c->px;
+      out_at(i, j, k) = mmk::kMu0 * (fld[pi] + mc[q]);
+    }
+  }
+  s = read_sticky(c);
+  if (s) return s;
+  return take_sticky(c);
+}
+
+mm_status mm_set_field(mm_ctx* c, int32_t field, const double* src) {
+  if (!c || !src) return MM_EINVAL;
+  if (field < 0 || field > 5) return fail(c, MM_EINVAL, "only E and H components can be set");
+  int ext[3];
+  field_extent(c, field, ext);
+  void* p = field < 3 ? c->E[field] : c->H[field - 3];
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  if (c->esz == 8) {
+    std::vector<double> h(c->nelem, 0.0);
+    for (int k = 0; k < ext[2]; ++k)
+      for (int j = 0; j < ext[1]; ++j)
+        for (int i = 0; i < ext[0]; ++i)
+          if (entry_interior(c, field, i, j, k))
+            h[pidx(c, i, j, k)] = src[(size_t)i + (size_t)ext[0] * ((size_t)j + (size_t)ext[1] * k)];
+    HIPCHECK(c, hipMemcpy(p, h.data(), c->nelem * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> h(c->nelem, 0.0f);
+    for (int k = 0; k < ext[2]; ++k)
+      for (int j = 0; j < ext[1]; ++j)
+        for (int i = 0; i < ext[0]; ++i)
+          if (entry_interior(c, field, i, j, k))
+            h[pidx(c, i, j, k)] = (float)src[(size_t)i + (size_t)ext[0] * ((size_t)j + (size_t)ext[1] * k)];
+    HIPCHECK(c, hipMemcpy(p, h.data(), c->nelem * 4, hipMemcpyHostToDevice));
+  }
+  return MM_OK;
+}
+
+mm_status mm_stats(mm_ctx* c, int32_t* iters, size_t cap, size_t* n) {
+  if (!c) return MM_EINVAL;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  const size_t tot = (size_t)c->substep;
+  if (n) *n = tot;
+  if (iters && tot) {
+    const size_t m = std::min(cap, tot);
+    if (c->nmag > 0) {
+      HIPCHECK(c, hipMemcpy(iters, c->d_iters, m * sizeof(int), hipMemcpyDeviceToHost));
+    } else {
+      for (size_t q = 0; q < m; ++q) iters[q] = c->fixed_iter > 0 ? c->fixed_iter : 1;
+    }
+  }
+  mm_status s = read_sticky(c);
+  if (s) return s;
+  return take_sticky(c);
+}
+
+mm_status mm_sync(mm_ctx* c) {
+  if (!c) return MM_EINVAL;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  mm_status s = read_sticky(c);
+  if (s) return s;
+  return take_sticky(c);
+}
+
+mm_status mm_info(const mm_ctx* c, int64_t out[8]) {
+  if (!c || !out) return MM_EINVAL;
+  out[0] = c->nmag;
+  out[1] = c->nwall;
+  out[2] = c->nsrc;
+  out[3] = c->px;
+  out[4] = c->py;
+  out[5] = c->pz;
+  out[6] = (int64_t)c->esz;
+  out[7] = (int64_t)c->dev_bytes;
+  return MM_OK;
+}
+
+mm_status mm_profile(mm_ctx* c, int32_t enable) {
+  if (!c) return MM_EINVAL;
+  c->prof = enable != 0;
+  return MM_OK;
+}
+
+mm_status mm_profile_read(mm_ctx* c, double ms[8], int64_t counts[8]) {
+  if (!c || !ms || !counts) return MM_EINVAL;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  for (int q = 0; q < 8; ++q) {
+    ms[q] = 0.0;
+    counts[q] = 0;
+  }
+  for (size_t q = 0; q < c->ev_used; ++q) {
+    float t = 0.f;
+    HIPCHECK(c, hipEventElapsedTime(&t, c->ev_pool[q].first, c->ev_pool[q].second));
+    ms[c->ev_class[q]] += t;
+    counts[c->ev_class[q]] += 1;
+  }
+  c->ev_used = 0;
+  return MM_OK;
+}
+
+const char* mm_last_error(const mm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void mm_destroy(mm_ctx* c) {
+  if (!c) return;
+  release(c);
+  delete c;
+}
+
+}  // extern "C"

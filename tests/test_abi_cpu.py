@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point declared in include/mm.h, and rejects bad arguments before
+touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2103_12819_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    if not os.path.exists(N.LIB_PATH):
+        pytest.skip("libmm.so not built (run __graft_entry__.build())")
+    return N.load()
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "mm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:mm_status|void|const char \*)\s*\*?\s*(mm_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_the_python_mirror():
+    assert declared_symbols() == sorted(N.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_the_header():
+    # sizes on x86-64 (LP64): int32 x6 + padding + doubles / pointers
+    assert C.sizeof(N.mm_grid) == 48
+    assert C.sizeof(N.mm_materials) == 7 * 8
+    assert C.sizeof(N.mm_bias) == 24
+    assert C.sizeof(N.mm_source) == 40
+    assert C.sizeof(N.mm_options) == 56
+    assert C.sizeof(N.mm_probe_desc) == 20
+
+
+def _init(lib, n=(8, 4, 4), d=(1e-6,) * 3, dt=None, tol=1e-10, max_iter=10, prec=0, Ms=None,
+          eps=None, bc=(0, 0, 0)):
+    ctx = C.c_void_p()
+    g = N.mm_grid(n[0], n[1], n[2], (C.c_int32 * 3)(*bc), d[0], d[1], d[2])
+    keep = [] if Ms is None else [Ms]
+    mat = N.mm_materials()
+    if Ms is not None:
+        mat.Ms = Ms.ctypes.data_as(C.POINTER(C.c_double))
+    if eps is not None:
+        keep.append(eps)
+        mat.eps_r = eps.ctypes.data_as(C.POINTER(C.c_double))
+    opt = N.mm_options()
+    opt.prec, opt.tol, opt.max_iter = prec, tol, max_iter
+    if dt is None:
+        dt = W.cfl_dt(0.9, *d)
+    st = lib.mm_init(C.byref(ctx), C.byref(g), dt, C.byref(mat), None, None, C.byref(opt))
+    return st, ctx
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dt=W.cfl_dt(1.01, 1e-6, 1e-6, 1e-6)),          # above the CFL limit
+    dict(dt=-1.0),
+    dict(tol=0.0),
+    dict(max_iter=0),
+    dict(prec=7),
+    dict(n=(0, 4, 4)),
+    dict(d=(1e-6, 0.0, 1e-6), dt=1e-16),
+    dict(bc=(0, 2, 0)),
+    dict(Ms=-np.ones(128)),
+    dict(eps=np.zeros(128)),
+    dict(eps=np.full(128, np.nan)),
+])
+def test_bad_arguments_are_rejected_before_any_device_work(kw):
+    lib = _lib()
+    st, ctx = _init(lib, **kw)
+    assert st == N.MM_EINVAL
+    assert not ctx.value
+
+
+def test_null_pointers_are_rejected():
+    lib = _lib()
+    assert lib.mm_init(None, None, 1.0, None, None, None, None) == N.MM_EINVAL
+    assert lib.mm_step(None, 1) == N.MM_EINVAL
+    assert lib.mm_sync(None) == N.MM_EINVAL
+    lib.mm_destroy(None)

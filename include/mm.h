@@ -166,10 +166,11 @@ mm_status mm_info(const mm_ctx *c, int64_t out[8]);
 
 /* Kernel timing.  mm_profile(c, 1) makes every later mm_step bracket each
  * kernel launch with a pair of HIP events on the context's stream (class
- * 0 e_update, 1 h_bulk, 2 hm_pre, 3 hm_iter, 4 add_source, 5 probes);
- * mm_profile(c, 0) stops recording.  mm_profile_read synchronises, writes
- * the summed elapsed milliseconds and the launch counts of each class to
- * ms[0..7] / counts[0..7] (classes 6, 7 unused) and discards the records. */
+ * 0 e_update, 1 h_bulk, 2 hm_pre, 3 hm_step, 4 hm_finish, 5 probes,
+ * 6 hm_commit); mm_profile(c, 0) stops recording.  mm_profile_read
+ * synchronises, writes the summed elapsed milliseconds and the launch counts
+ * of each class to ms[0..7] / counts[0..7] (class 7 unused) and discards
+ * the records. */
 mm_status mm_profile(mm_ctx *c, int32_t enable);
 mm_status mm_profile_read(mm_ctx *c, double ms[8], int64_t counts[8]);
 

@@ -74,7 +74,7 @@ def d_down(a, ax, per):
         return a - np.roll(a, 1, axis=ax)
     shp = list(a.shape)
     shp[ax] += 1
-    out = np.zeros(shp)
+    out = np.zeros(shp, dtype=np.result_type(a, np.float64))
     out[_sl(ax, slice(1, -1))] = a[_sl(ax, slice(1, None))] - a[_sl(ax, slice(0, -1))]
     return out
 
@@ -86,7 +86,7 @@ def s_down(a, ax, per, clamp=False):
         return np.roll(a, 1, axis=ax) + a
     shp = list(a.shape)
     shp[ax] += 1
-    out = np.zeros(shp)
+    out = np.zeros(shp, dtype=np.result_type(a, np.float64))
     out[_sl(ax, slice(1, -1))] = a[_sl(ax, slice(0, -1))] + a[_sl(ax, slice(1, None))]
     if clamp:
         out[_sl(ax, 0)] = 2.0 * a[_sl(ax, 0)]
@@ -101,8 +101,8 @@ def s_up(a, ax, per):
     return a[_sl(ax, slice(0, -1))] + a[_sl(ax, slice(1, None))]
 
 
-def to_ijk(a):
-    return np.asarray(a, dtype=np.float64).transpose(2, 1, 0)
+def to_ijk(a, dtype=np.float64):
+    return np.asarray(a, dtype=dtype).transpose(2, 1, 0)
 
 
 def to_host(a):
@@ -129,10 +129,13 @@ def vacus_solve(a, b):
 
 
 def renormalise(m, Ms):
-    """N(M) = M * (Ms / |M|)  (Sec. 3.2)."""
+    """N(M) = M * (Ms / |M|)  (Sec. 3.2).  |M| is written as sqrt(M.M) (no
+    conjugation), so the function is analytic and complex-step derivatives
+    pass through it."""
     nrm = np.sqrt(dot(m, m))
+    pos = np.real(nrm) > 0
     with np.errstate(invalid="ignore", divide="ignore"):
-        s = np.where(nrm > 0, Ms / np.where(nrm > 0, nrm, 1.0), 0.0)
+        s = np.where(pos, Ms / np.where(pos, nrm, 1.0), 0.0)
     return [m[c] * s for c in range(3)]
 
 
@@ -153,12 +156,15 @@ class Simulation:
     uniform bias `H0`, optional soft source (comp, profile, f0, Tp, t0),
     per-axis periodic flags, sub-step tolerance / iteration cap, and
     `fixed_iter` (> 0: exactly that many iterations per sub-step).
+    `dtype` complex128 runs the same arithmetic on complex numbers (all
+    decisions use real parts), for complex-step derivatives in the tests.
     """
 
     def __init__(self, n, d, dt, eps_r=None, sigma=None, mu_r=None, Ms=None,
                  alpha=None, gamma=None, m0_dir=None, H0=(0.0, 0.0, 0.0),
                  source=None, periodic=(False, False, False), tol=1e-10,
-                 max_iter=100, fixed_iter=0, raise_on_noconv=False):
+                 max_iter=100, fixed_iter=0, raise_on_noconv=False, dtype=np.float64):
+        self.dtype = np.dtype(dtype)
         self.n = tuple(int(v) for v in n)
         self.d = tuple(float(v) for v in d)
         self.dt = float(dt)
@@ -173,8 +179,8 @@ class Simulation:
 
         def cmap(a, default):
             if a is None:
-                return np.full(shp, float(default))
-            a = to_ijk(a)
+                return np.full(shp, float(default), dtype=self.dtype)
+            a = to_ijk(a, self.dtype)
             assert a.shape == shp
             return a
 
@@ -188,15 +194,16 @@ class Simulation:
             m0 = [np.zeros(shp), np.zeros(shp), np.ones(shp)]
         else:
             m0 = [to_ijk(np.asarray(m0_dir)[c]) for c in range(3)]
+        self.m0_dir = m0
         self._prepare(m0)
 
         # fields on the Yee grid (Sec. 3.1)
-        self.E = [np.zeros(self.edge_shape(c)) for c in range(3)]
-        self.H = [np.zeros(self.face_shape(c)) for c in range(3)]
+        self.E = [np.zeros(self.edge_shape(c), dtype=self.dtype) for c in range(3)]
+        self.H = [np.zeros(self.face_shape(c), dtype=self.dtype) for c in range(3)]
         self.src = None
         if source is not None:
             comp, prof, f0, Tp, t0 = source
-            prof = to_ijk(prof)
+            prof = to_ijk(prof, self.dtype)
             assert prof.shape == self.edge_shape(comp)
             self.src = (int(comp), prof * self.e_interior[comp], float(f0), float(Tp), float(t0))
         self.step_count = 0
@@ -260,7 +267,7 @@ class Simulation:
         # faces: Ms as the mean of the 2 adjacent cells, mu likewise; alpha and
         # gamma over the magnetic neighbour cells only; M0 as the mean of the
         # cell-centred M0 = Ms * m0_dir, renormalised to Ms_f
-        mag_c = (self.Ms_c > 0).astype(np.float64)
+        mag_c = (np.real(self.Ms_c) > 0).astype(np.float64)
         self.Ms_f, self.mu_f, self.alpha_f, self.gamma_f = [], [], [], []
         self.mag, self.evolve, self.M = [], [], []
         for f in range(3):
@@ -272,10 +279,10 @@ class Simulation:
                               / np.where(cnt > 0, cnt, 1.0), 0.0)
                 gf = np.where(cnt > 0, s_down(self.gamma_c * mag_c, f, per[f], clamp=True)
                               / np.where(cnt > 0, cnt, 1.0), 0.0)
-            mag = Msf > 0
+            mag = np.real(Msf) > 0
             Mf = [0.5 * s_down(self.Ms_c * m0[c], f, per[f], clamp=True) for c in range(3)]
             nrm = np.sqrt(dot(Mf, Mf))
-            if np.any(mag & (nrm == 0)):
+            if np.any(mag & (np.abs(nrm) == 0)):
                 raise ValueError("initial magnetisation averages to zero on a magnetic face")
             Mf = [np.where(mag, v, 0.0) for v in renormalise(Mf, Msf)]
             self.Ms_f.append(Msf)
@@ -291,10 +298,10 @@ class Simulation:
         """Set E and/or H from host-layout arrays; PEC-wall entries are zeroed."""
         if E is not None:
             for c in range(3):
-                self.E[c] = np.where(self.e_interior[c], to_ijk(E[c]), 0.0)
+                self.E[c] = np.where(self.e_interior[c], to_ijk(E[c], self.dtype), 0.0)
         if H is not None:
             for f in range(3):
-                self.H[f] = np.where(self.h_interior[f], to_ijk(H[f]), 0.0)
+                self.H[f] = np.where(self.h_interior[f], to_ijk(H[f], self.dtype), 0.0)
 
     def field(self, name):
         """Host-layout copy of a field: Ex..Hz, M<family><comp> (e.g. 'Myz'), Bx..Bz."""
@@ -350,7 +357,10 @@ class Simulation:
         return out
 
     # ---- Step 1 / Step 3: the iterative H-M sub-step (Sec. 3.2.2) ----------
-    def hm_substep(self, C):
+    def hm_substep(self, C, trace=None):
+        """One H-M sub-step from the current (H, M) with face curl C.  With a
+        dict `trace`, records its inputs and the iterate H^{(r-1)} read by each
+        iteration r (what the reverse sweep replays)."""
         h = 0.5 * self.dt
         Hs = [a.copy() for a in self.H]
         Ms0 = [[v.copy() for v in self.M[f]] for f in range(3)]
@@ -369,11 +379,18 @@ class Simulation:
             kappa.append(kap)
             q.append(Hs[f] + Ms0[f][f] - (h / MU0) * C[f])
         Hprev, Mprev = Hs, Ms0
+        if trace is not None:
+            trace["Hs"] = [a.copy() for a in Hs]
+            trace["Ms0"] = [[v.copy() for v in Ms0[f]] for f in range(3)]
+            trace["C"] = [a.copy() for a in C]
+            trace["Hprevs"] = []
         r = 0
         limit = self.fixed_iter if self.fixed_iter > 0 else self.max_iter
         converged = False
         while r < limit:
             r += 1
+            if trace is not None:
+                trace["Hprevs"].append(Hprev)
             Hr, Mr = [], []
             parts = [0.0]
             for f in range(3):
@@ -387,7 +404,8 @@ class Simulation:
                 if ev.any():
                     with np.errstate(invalid="ignore"):
                         for c in range(3):
-                            parts.append(float(np.max(np.abs(Mn[c] - Mprev[f][c])[ev] / self.Ms_f[f][ev])))
+                            parts.append(float(np.max(np.abs(Mn[c] - Mprev[f][c])[ev]
+                                                      / np.abs(self.Ms_f[f][ev]))))
                 Hr.append(Hn)
                 Mr.append(Mn)
             # np.max propagates NaN, so a non-finite iterate shows up here
@@ -419,12 +437,21 @@ class Simulation:
             self.E[c] = np.where(self.e_interior[c], self.ca[c] * self.E[c] + self.cb[c] * rhs, 0.0)
 
     # ---- one full step n -> n+1 --------------------------------------------
-    def step(self, nsteps=1):
+    def step(self, nsteps=1, tape=None):
+        """Advance `nsteps` steps.  With a list `tape`, appends per step the
+        states and sub-step traces the reverse sweep needs."""
         for _ in range(nsteps):
-            self.hm_substep(self.curl_E(self.E))     # Step 1 with curl E^n
-            self.e_update()                          # Step 2
-            self.hm_substep(self.curl_E(self.E))     # Step 3 with curl E^{n+1}
+            rec = None
+            if tape is not None:
+                rec = {"n": self.step_count, "E0": [a.copy() for a in self.E], "tr1": {}, "tr3": {}}
+            self.hm_substep(self.curl_E(self.E), trace=None if rec is None else rec["tr1"])  # Step 1
+            self.e_update()                                                                  # Step 2
+            self.hm_substep(self.curl_E(self.E), trace=None if rec is None else rec["tr3"])  # Step 3
             self.step_count += 1
+            if rec is not None:
+                rec["E1"] = [a.copy() for a in self.E]
+                rec["H1"] = [a.copy() for a in self.H]
+                tape.append(rec)
             self._record_probes()
 
     # ---- probes -------------------------------------------------------------
@@ -442,18 +469,18 @@ class Simulation:
         im1 = (i0 - 1) % self.n[0]
         hz = 0.5 * (self.H[2][im1] + self.H[2][i0 % self.n[0]])
         hy = 0.5 * (self.H[1][im1] + self.H[1][i0 % self.n[0]])
-        s = float(np.sum(self.E[1][i0] * hz)) - float(np.sum(self.E[2][i0] * hy))
+        s = np.sum(self.E[1][i0] * hz) - np.sum(self.E[2][i0] * hy)
         return dy * dz * s
 
     def point_value(self, field, i, j, k):
         if field < 3:
-            return float(self.E[field][i, j, k])
+            return self.E[field][i, j, k]
         if field < 6:
-            return float(self.H[field - 3][i, j, k])
+            return self.H[field - 3][i, j, k]
         if field < 15:
             f, c = divmod(field - 6, 3)
-            return float(self.M[f][c][i, j, k])
-        return float(self.B_normal(field - 15)[i, j, k])
+            return self.M[f][c][i, j, k]
+        return self.B_normal(field - 15)[i, j, k]
 
     def _record_probes(self):
         for p in self.probes:
@@ -463,7 +490,7 @@ class Simulation:
                 p["series"].append(self.point_value(p["field"], p["i"], p["j"], p["k"]))
 
     def probe_series(self, pid):
-        return np.array(self.probes[pid]["series"], dtype=np.float64)
+        return np.array(self.probes[pid]["series"], dtype=self.dtype)
 
     def probe_integral(self, pid):
         """S = sum_n dt * P^n, accumulated in step order."""

@@ -193,7 +193,7 @@ class Sim:
         keys = ["n_mag", "n_wall_mag", "n_src", "px", "py", "pz", "elem_bytes", "device_bytes"]
         return dict(zip(keys, list(out)))
 
-    KERNEL_CLASSES = ["e_update", "h_bulk", "hm_pre", "hm_iter", "add_source", "probes"]
+    KERNEL_CLASSES = ["e_update", "h_bulk", "hm_pre", "hm_step", "hm_finish", "probes", "hm_commit"]
 
     def profile(self, enable=True):
         """Bracket every later kernel launch with HIP events (see mm_profile)."""

@@ -2,9 +2,9 @@
 //
 // Scheme: Yao, Jambunathan, Zeng & Nonaka, Sec. 3.2.2 (second-order coupled
 // scheme) on the Yee grid of Sec. 3.1.  One step is
-//   Step 1: H-M sub-step with curl E^n     (hm_pre -> h_bulk -> hm_iter)
+//   Step 1: H-M sub-step with curl E^n     (hm_pre -> h_bulk -> hm_step.. -> hm_finish -> hm_commit)
 //   Step 2: E update with the soft source   (e_update)
-//   Step 3: H-M sub-step with curl E^{n+1} (hm_pre -> h_bulk -> hm_iter)
+//   Step 3: H-M sub-step with curl E^{n+1} (the same sequence)
 //   probes at level n+1                     (probe_points, probe_flux)
 //
 // Storage: every field array (and every cell map) lives in one padded
@@ -19,13 +19,16 @@
 // Magnetic faces are handled from a compact face list: hm_pre builds the
 // iteration-invariant quantities of eq:llg_tra5/6 and eq:iterate_H and does
 // iteration r = 1 (which needs only H^s); h_bulk applies the non-magnetic
-// Faraday update to every face; hm_iter is a cooperative persistent kernel
-// that commits the magnetic H, then runs Jacobi iterations r = 2, 3, ...
-// with a grid-wide max of |dM|/Ms after each one, all on the device.
+// Faraday update to every face; the Jacobi iterations r = 2, 3, ... then
+// ping-pong the magnetic faces' H between H and a shadow array A (odd r
+// write A, even r write H; non-magnetic neighbours are always read from H),
+// so an iteration needs no commit pass.  They run as ordinary launches
+// (hm_step) that return at once when the device-side stopping test on the
+// max of |dM|/Ms has fired; hm_finish continues the iteration if the
+// launches enqueued were too few, and hm_commit brings the final H home.
 #pragma once
 
 #include <hip/hip_runtime.h>
-#include <hip/hip_cooperative_groups.h>
 #include <stdint.h>
 
 namespace mmk {
@@ -181,7 +184,7 @@ __global__ __launch_bounds__(256) void e_update(Geo g, T* __restrict__ Ex, T* __
 // ---------------------------------------------------------------------------
 // H half step with the non-magnetic Faraday law (eq:Faraday3 with the local
 // mu, Sec. 3.2.2): H <- H - (dt/2 mu_f) curl E on every interior face.
-// Magnetic faces are overwritten afterwards by hm_iter.
+// Magnetic faces are overwritten afterwards by the iteration.
 // ---------------------------------------------------------------------------
 template <typename T, bool MU>
 __global__ __launch_bounds__(256) void h_bulk(Geo g, T* __restrict__ Hx, T* __restrict__ Hy,
@@ -247,20 +250,30 @@ template <typename T>
 struct Fields {
   T* E[3];
   T* H[3];
+  T* A[3];   // shadow H on magnetic faces (ping-pong partner of H during the iteration)
 };
 
 struct Mag {
-  const int* idx;       // padded index of the face
-  const double* Ms;     // face Ms
-  const double* kap;    // mu0 * gamma_f * dt / 4 (signed gamma)
-  const double* aoms;   // alpha_f / Ms_f
-  double* M[3];         // current iterate (components x, y, z)
-  double* b[3];         // b of eq:llg_tra6 (signed-gamma form), per sub-step
-  double* d[3];         // (alpha/Ms) M^s, per sub-step
-  double* q;            // H^s_n + M^s_n - (dt/2 mu0) curl E, per sub-step
-  double* hnew;         // H^{(r)}_n of the latest iteration
-  int off1, off2, n;    // family offsets and the number of evolving faces
+  const int* idx;            // padded index of the face
+  const unsigned char* nbm;  // bit q: transverse neighbour q is an evolving magnetic face
+  const double* Ms;          // face Ms
+  const double* kap;         // mu0 * gamma_f * dt / 4 (signed gamma)
+  const double* aoms;        // alpha_f / Ms_f
+  double* M[3];              // current iterate (components x, y, z)
+  double* b[3];              // b of eq:llg_tra6 (signed-gamma form), per sub-step
+  double* d[3];              // (alpha/Ms) M^s, per sub-step
+  double* q;                 // H^s_n + M^s_n - (dt/2 mu0) curl E, per sub-step
+  double* hlog;              // optional: H^{(r)} of every face, slot r-1 (for the adjoint)
+  int hlog_cap;              // number of slots in hlog
+  int off1, off2, n;         // family offsets and the number of evolving faces
 };
+
+// Record H^{(r)} of face t in the iterate log (adjoint recompute only).
+__device__ __forceinline__ void log_iterate(const Mag& m, int r, int t, double v, int* err) {
+  if (!m.hlog) return;
+  if (r <= m.hlog_cap) m.hlog[(size_t)(r - 1) * m.n + t] = v;
+  else atomicOr(err, 8);
+}
 
 __device__ __forceinline__ void face_ijk(const Geo& g, int c, int& i, int& j, int& k) {
   k = c / g.sz;
@@ -269,7 +282,7 @@ __device__ __forceinline__ void face_ijk(const Geo& g, int c, int& i, int& j, in
   i = r - j * g.px;
 }
 
-// curl E at face (i,j,k) of family f.
+// curl E at face (i,j,k) of family f (FP64, reference operation order).
 template <typename T>
 __device__ __forceinline__ double curl_e_face(const Geo& g, const Fields<T>& F, int f, int i, int j,
                                               int k) {
@@ -290,35 +303,44 @@ __device__ __forceinline__ double curl_e_face(const Geo& g, const Fields<T>& F, 
   }
 }
 
+// Where iteration r reads H^{(r-1)}: evolving magnetic faces from `alt`
+// (bit q of `mask` set for transverse neighbour q), all other faces from
+// `base`.  With alt == base every read comes from one array.
+template <typename T>
+struct HRead {
+  const T* base[3];
+  const T* alt[3];
+  unsigned mask;
+  __device__ __forceinline__ double v(int comp, int c, int q) const {
+    return D(((mask >> q) & 1u) ? alt[comp][c] : base[comp][c]);
+  }
+};
+
 // H_eff = H0 + H_EM at an interior face of family f: own normal H plus the
 // two transverse components as four-point means (Sec. 3.1), each paired
 // along the face normal first and then along the component's own axis.
+// Neighbour q numbering: first transverse component q = 0..3, second 4..7,
+// in the order (f-1, c), (f, c), (f-1, c+1), (f, c+1).
 template <typename T>
-__device__ __forceinline__ void h_eff(const Geo& g, const Fields<T>& F, int f, int i, int j, int k,
-                                      double H0x, double H0y, double H0z, double he[3]) {
+__device__ __forceinline__ void h_eff(const Geo& g, const HRead<T>& R, double own, int f, int i, int j,
+                                      int k, double H0x, double H0y, double H0z, double he[3]) {
   const bool pxp = g.per & 1, pyp = g.per & 2, pzp = g.per & 4;
   const int c = at(g, i, j, k);
   if (f == 0) {
     const int im = dn(i, g.nx, pxp), jp = up(j, g.ny, pyp), kp = up(k, g.nz, pzp);
-    const T* Hy = F.H[1];
-    const T* Hz = F.H[2];
-    he[0] = D(F.H[0][c]) + H0x;
-    he[1] = 0.25 * ((D(Hy[at(g, im, j, k)]) + D(Hy[c])) + (D(Hy[at(g, im, jp, k)]) + D(Hy[at(g, i, jp, k)]))) + H0y;
-    he[2] = 0.25 * ((D(Hz[at(g, im, j, k)]) + D(Hz[c])) + (D(Hz[at(g, im, j, kp)]) + D(Hz[at(g, i, j, kp)]))) + H0z;
+    he[0] = own + H0x;
+    he[1] = 0.25 * ((R.v(1, at(g, im, j, k), 0) + R.v(1, c, 1)) + (R.v(1, at(g, im, jp, k), 2) + R.v(1, at(g, i, jp, k), 3))) + H0y;
+    he[2] = 0.25 * ((R.v(2, at(g, im, j, k), 4) + R.v(2, c, 5)) + (R.v(2, at(g, im, j, kp), 6) + R.v(2, at(g, i, j, kp), 7))) + H0z;
   } else if (f == 1) {
     const int jm = dn(j, g.ny, pyp), ip = up(i, g.nx, pxp), kp = up(k, g.nz, pzp);
-    const T* Hx = F.H[0];
-    const T* Hz = F.H[2];
-    he[0] = 0.25 * ((D(Hx[at(g, i, jm, k)]) + D(Hx[c])) + (D(Hx[at(g, ip, jm, k)]) + D(Hx[at(g, ip, j, k)]))) + H0x;
-    he[1] = D(F.H[1][c]) + H0y;
-    he[2] = 0.25 * ((D(Hz[at(g, i, jm, k)]) + D(Hz[c])) + (D(Hz[at(g, i, jm, kp)]) + D(Hz[at(g, i, j, kp)]))) + H0z;
+    he[0] = 0.25 * ((R.v(0, at(g, i, jm, k), 0) + R.v(0, c, 1)) + (R.v(0, at(g, ip, jm, k), 2) + R.v(0, at(g, ip, j, k), 3))) + H0x;
+    he[1] = own + H0y;
+    he[2] = 0.25 * ((R.v(2, at(g, i, jm, k), 4) + R.v(2, c, 5)) + (R.v(2, at(g, i, jm, kp), 6) + R.v(2, at(g, i, j, kp), 7))) + H0z;
   } else {
     const int km = dn(k, g.nz, pzp), ip = up(i, g.nx, pxp), jp = up(j, g.ny, pyp);
-    const T* Hx = F.H[0];
-    const T* Hy = F.H[1];
-    he[0] = 0.25 * ((D(Hx[at(g, i, j, km)]) + D(Hx[c])) + (D(Hx[at(g, ip, j, km)]) + D(Hx[at(g, ip, j, k)]))) + H0x;
-    he[1] = 0.25 * ((D(Hy[at(g, i, j, km)]) + D(Hy[c])) + (D(Hy[at(g, i, jp, km)]) + D(Hy[at(g, i, jp, k)]))) + H0y;
-    he[2] = D(F.H[2][c]) + H0z;
+    he[0] = 0.25 * ((R.v(0, at(g, i, j, km), 0) + R.v(0, c, 1)) + (R.v(0, at(g, ip, j, km), 2) + R.v(0, at(g, ip, j, k), 3))) + H0x;
+    he[1] = 0.25 * ((R.v(1, at(g, i, j, km), 4) + R.v(1, c, 5)) + (R.v(1, at(g, i, jp, km), 6) + R.v(1, at(g, i, jp, k), 7))) + H0y;
+    he[2] = own + H0z;
   }
 }
 
@@ -364,6 +386,7 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v
     const int nw = (blockDim.x + 63) >> 6;
     for (int q = 1; q < nw; ++q) v = wmax[q] > v ? wmax[q] : v;
   }
+  __syncthreads();
   return v;   // valid in thread 0
 }
 
@@ -371,11 +394,78 @@ __device__ __forceinline__ int face_family(const Mag& m, int t) {
   return t < m.off1 ? 0 : (t < m.off2 ? 1 : 2);
 }
 
-// Sub-step set-up and iteration r = 1 (which only needs H^s).
+__device__ __forceinline__ unsigned long long load_u64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Per-sub-step control block (one per sub-step parity):
+//   ctl[0]      the final iteration count once the stopping rule has fired (0 before)
+//   ctl[r]      max over faces of the residual bits of iteration r (r >= 1)
+struct Ctl {
+  unsigned long long* cur;
+  unsigned long long* next;   // the other sub-step's block, cleared by hm_finish
+  int nres;
+  double tol;
+  int max_iter, fixed_iter;
+};
+
+// Stopping rule of Sec. 3.2.2 after iteration r_done has finished:
+// stop on a non-finite residual, on residual < tol, at max_iter, or (fixed
+// mode) after fixed_iter iterations.
+__device__ __forceinline__ bool stop_after(const Ctl& C, int r_done, bool& bad) {
+  const double rv = __longlong_as_double((long long)load_u64(&C.cur[r_done]));
+  bad = !(rv <= 1.0e308);
+  if (bad) return true;
+  if (C.fixed_iter > 0) return r_done >= C.fixed_iter;
+  return (rv < C.tol) || (r_done >= C.max_iter);
+}
+
+// One Jacobi iteration r >= 2 for the faces t = t0, t0 + stride, ...; reads
+// H^{(r-1)} through `Rd` and writes H^{(r)} into `out`.  Returns the max of
+// the residual bits.
+template <typename T>
+__device__ __forceinline__ unsigned long long iterate_faces(const Geo& g, const Mag& m, const Fields<T>& F,
+                                                            T* const* prev, T* const* out, int t0, int stride,
+                                                            double H0x, double H0y, double H0z, int r,
+                                                            int* err) {
+  unsigned long long lb = 0;
+  for (int t = t0; t < m.n; t += stride) {
+    const int f = face_family(m, t);
+    const int c = m.idx[t];
+    int i, j, k;
+    face_ijk(g, c, i, j, k);
+    HRead<T> Rd;
+    for (int a = 0; a < 3; ++a) {
+      Rd.base[a] = F.H[a];
+      Rd.alt[a] = prev[a];
+    }
+    Rd.mask = m.nbm[t];
+    double he[3];
+    h_eff(g, Rd, D(prev[f][c]), f, i, j, k, H0x, H0y, H0z, he);
+    const double Ms = m.Ms[t];
+    const double d[3] = {m.d[0][t], m.d[1][t], m.d[2][t]};
+    const double b[3] = {m.b[0][t], m.b[1][t], m.b[2][t]};
+    const double mo[3] = {m.M[0][t], m.M[1][t], m.M[2][t]};
+    double mn[3];
+    llg_solve(he, m.kap[t], d, b, Ms, mn);
+    const T hv = (T)(m.q[t] - mn[f]);
+    out[f][c] = hv;
+    log_iterate(m, r, t, D(hv), err);
+    for (int q3 = 0; q3 < 3; ++q3) {
+      m.M[q3][t] = mn[q3];
+      const unsigned long long bb = rbits(fabs(mn[q3] - mo[q3]) / Ms);
+      lb = bb > lb ? bb : lb;
+    }
+  }
+  return lb;
+}
+
+// Sub-step set-up and iteration r = 1 (which only needs H^s): the
+// iteration-invariant b, d of eq:llg_tra5/6 and q of eq:iterate_H, then
+// M^{(1)} in place and H^{(1)} into the shadow array A.
 template <typename T>
 __global__ __launch_bounds__(256) void hm_pre(Geo g, Fields<T> F, Mag m, double hmu0, double H0x,
-                                             double H0y, double H0z,
-                                             unsigned long long* __restrict__ res1) {
+                                             double H0y, double H0z, Ctl C, int* err) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long rb = 0;
   if (t < m.n) {
@@ -383,9 +473,16 @@ __global__ __launch_bounds__(256) void hm_pre(Geo g, Fields<T> F, Mag m, double 
     const int c = m.idx[t];
     int i, j, k;
     face_ijk(g, c, i, j, k);
-    const double C = curl_e_face(g, F, f, i, j, k);
+    const double Cf = curl_e_face(g, F, f, i, j, k);
+    HRead<T> Rd;
+    for (int a = 0; a < 3; ++a) {
+      Rd.base[a] = F.H[a];
+      Rd.alt[a] = F.H[a];
+    }
+    Rd.mask = 0;
+    const double hs = D(F.H[f][c]);
     double he[3];
-    h_eff(g, F, f, i, j, k, H0x, H0y, H0z, he);
+    h_eff(g, Rd, hs, f, i, j, k, H0x, H0y, H0z, he);
     const double Ms = m.Ms[t], kap = m.kap[t], aoms = m.aoms[t];
     const double ms[3] = {m.M[0][t], m.M[1][t], m.M[2][t]};
     // M^s x H_eff^s
@@ -394,100 +491,132 @@ __global__ __launch_bounds__(256) void hm_pre(Geo g, Fields<T> F, Mag m, double 
     const double mz = ms[0] * he[1] - ms[1] * he[0];
     const double b[3] = {ms[0] + kap * mx, ms[1] + kap * my, ms[2] + kap * mz};
     const double d[3] = {aoms * ms[0], aoms * ms[1], aoms * ms[2]};
-    const double q = D(F.H[f][c]) + ms[f] - hmu0 * C;
+    const double q = hs + ms[f] - hmu0 * Cf;
     double mn[3];
     llg_solve(he, kap, d, b, Ms, mn);
-    const double hn = q - mn[f];
-    double r = fabs(mn[0] - ms[0]) / Ms;
-    unsigned long long bits = rbits(r);
-    unsigned long long b1 = rbits(fabs(mn[1] - ms[1]) / Ms);
-    unsigned long long b2 = rbits(fabs(mn[2] - ms[2]) / Ms);
-    bits = b1 > bits ? b1 : bits;
-    bits = b2 > bits ? b2 : bits;
-    rb = bits;
+    const T hv = (T)(q - mn[f]);
+    F.A[f][c] = hv;
+    log_iterate(m, 1, t, D(hv), err);
     for (int q3 = 0; q3 < 3; ++q3) {
+      const unsigned long long bb = rbits(fabs(mn[q3] - ms[q3]) / Ms);
+      rb = bb > rb ? bb : rb;
       m.b[q3][t] = b[q3];
       m.d[q3][t] = d[q3];
       m.M[q3][t] = mn[q3];
     }
     m.q[t] = q;
-    m.hnew[t] = hn;
   }
   rb = block_max_u64(rb);
-  if (threadIdx.x == 0 && rb) atomicMax(res1, rb);
+  if (threadIdx.x == 0 && rb) atomicMax(&C.cur[1], rb);
 }
 
-__device__ __forceinline__ unsigned long long load_u64(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Iterations r = 2, 3, ... of the H-M sub-step (Jacobi: every face reads its
-// neighbours' H^{(r-1)}), with the grid-wide stopping test of Sec. 3.2.2
-// after each one.  Cooperative launch; every wave reaches each grid.sync and
-// the loop ends after at most max(max_iter, fixed_iter) iterations.
+// Iteration r >= 2 as an ordinary launch.  Every thread evaluates the
+// stopping rule on iteration r-1's residual (the same value everywhere) and
+// the whole grid returns at once when it fires; block 0 then records the
+// final count.  H^{(r)} goes to H for even r and to A for odd r.
 template <typename T>
-__global__ __launch_bounds__(256) void hm_iter(Geo g, Fields<T> F, Mag m, double H0x, double H0y,
-                                              double H0z, unsigned long long* __restrict__ res,
-                                              unsigned long long* __restrict__ res_next, int nres,
-                                              double tol, int max_iter, int fixed_iter,
-                                              int* __restrict__ iters_out, int* __restrict__ err) {
-  namespace cg = cooperative_groups;
-  cg::grid_group grid = cg::this_grid();
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nth = gridDim.x * blockDim.x;
-  if (blockIdx.x == 0)
-    for (int s = threadIdx.x; s < nres; s += blockDim.x) res_next[s] = 0ull;
-  for (int t = tid; t < m.n; t += nth) F.H[face_family(m, t)][m.idx[t]] = (T)m.hnew[t];
-  __threadfence();
-  grid.sync();
-  __threadfence();
-  int r = 1;
-  double rv = 0.0;
-  for (;;) {
-    rv = __longlong_as_double((long long)load_u64(&res[r]));
-    const bool bad = !(rv <= 1.0e308);          // NaN or +Inf
-    bool stop;
-    if (bad) stop = true;
-    else if (fixed_iter > 0) stop = r >= fixed_iter;
-    else stop = (rv < tol) || (r >= max_iter);
-    if (stop) break;
-    ++r;
-    unsigned long long lb = 0;
-    for (int t = tid; t < m.n; t += nth) {
-      const int f = face_family(m, t);
-      const int c = m.idx[t];
-      int i, j, k;
-      face_ijk(g, c, i, j, k);
-      double he[3];
-      h_eff(g, F, f, i, j, k, H0x, H0y, H0z, he);
-      const double Ms = m.Ms[t];
-      const double d[3] = {m.d[0][t], m.d[1][t], m.d[2][t]};
-      const double b[3] = {m.b[0][t], m.b[1][t], m.b[2][t]};
-      const double mo[3] = {m.M[0][t], m.M[1][t], m.M[2][t]};
-      double mn[3];
-      llg_solve(he, m.kap[t], d, b, Ms, mn);
-      m.hnew[t] = m.q[t] - mn[f];
-      for (int q3 = 0; q3 < 3; ++q3) {
-        m.M[q3][t] = mn[q3];
-        const unsigned long long bb = rbits(fabs(mn[q3] - mo[q3]) / Ms);
-        lb = bb > lb ? bb : lb;
+__global__ __launch_bounds__(256) void hm_step(Geo g, Fields<T> F, Mag m, double H0x, double H0y,
+                                              double H0z, Ctl C, int r, int* err) {
+  if (load_u64(&C.cur[0]) != 0ull) return;
+  bool bad;
+  if (stop_after(C, r - 1, bad)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) C.cur[0] = (unsigned long long)(r - 1);
+    return;
+  }
+  T* const* prev = (r & 1) ? F.H : F.A;
+  T* const* out = (r & 1) ? F.A : F.H;
+  unsigned long long lb = iterate_faces(g, m, F, prev, out, blockIdx.x * blockDim.x + threadIdx.x,
+                                        gridDim.x * blockDim.x, H0x, H0y, H0z, r, err);
+  lb = block_max_u64(lb);
+  if (threadIdx.x == 0 && lb) atomicMax(&C.cur[r], lb);
+}
+
+// Bounded-spin barrier across the (small, co-resident) grid of hm_finish.
+// bar[0] arrival count, bar[1] generation.  Returns false on timeout.
+__device__ __forceinline__ bool grid_barrier(unsigned int* bar) {
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    ok = 1;
+    __threadfence();
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (atomicAdd(&bar[0], 1u) == gridDim.x - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      atomicAdd(&bar[1], 1u);
+    } else {
+      long n = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++n > 10000000L) {
+          ok = 0;
+          break;
+        }
       }
     }
-    lb = block_max_u64(lb);
-    if (threadIdx.x == 0 && lb) atomicMax(&res[r], lb);
-    __threadfence();
-    grid.sync();
-    __threadfence();
-    for (int t = tid; t < m.n; t += nth) F.H[face_family(m, t)][m.idx[t]] = (T)m.hnew[t];
-    __threadfence();
-    grid.sync();
     __threadfence();
   }
-  if (tid == 0) {
-    iters_out[0] = r;
-    const bool bad = !(rv <= 1.0e308);
-    if (bad) atomicOr(err, 2);
-    else if (fixed_iter <= 0 && !(rv < tol)) atomicOr(err, 1);
+  __syncthreads();
+  return ok != 0;
+}
+
+// If the launches enqueued have not met the stopping rule, keep iterating
+// here (one barrier per iteration; the grid is at most one block per CU, so
+// it is resident as a whole).  Either way ctl[0] ends holding the final
+// count.  Returns at once in the common case.
+template <typename T>
+__global__ __launch_bounds__(256) void hm_finish(Geo g, Fields<T> F, Mag m, double H0x, double H0y,
+                                                double H0z, Ctl C, int r_next, unsigned int* bar, int* err) {
+  if (load_u64(&C.cur[0]) != 0ull) return;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nth = gridDim.x * blockDim.x;
+  bool bad = false;
+  int r = r_next;
+  for (;;) {
+    if (stop_after(C, r - 1, bad)) break;
+    T* const* prev = (r & 1) ? F.H : F.A;
+    T* const* out = (r & 1) ? F.A : F.H;
+    unsigned long long lb = iterate_faces(g, m, F, prev, out, tid, nth, H0x, H0y, H0z, r, err);
+    lb = block_max_u64(lb);
+    if (threadIdx.x == 0 && lb) atomicMax(&C.cur[r], lb);
+    if (!grid_barrier(bar)) {
+      if (threadIdx.x == 0) atomicOr(err, 4);
+      r += 1;
+      break;
+    }
+    ++r;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) C.cur[0] = (unsigned long long)(r - 1);
+}
+
+// End of a sub-step: bring the final magnetic H into H when it sits in A
+// (odd count), record the count and the sticky flags, and clear the other
+// sub-step's control block.
+template <typename T>
+__global__ __launch_bounds__(256) void hm_commit(Fields<T> F, Mag m, Ctl C, int* iters_out, int* ring,
+                                                int* err) {
+  const int rfin = (int)load_u64(&C.cur[0]);
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rfin & 1)
+    for (int t = tid; t < m.n; t += gridDim.x * blockDim.x) {
+      const int f = face_family(m, t);
+      F.H[f][m.idx[t]] = F.A[f][m.idx[t]];
+    }
+  if (blockIdx.x == 0) {
+    for (int s2 = threadIdx.x; s2 < C.nres; s2 += blockDim.x) C.next[s2] = 0ull;
+    if (threadIdx.x == 0) {
+      iters_out[0] = rfin;
+      ring[0] = rfin;
+      bool bad;
+      stop_after(C, rfin, bad);
+      int e = 0;
+      if (bad) e |= 2;
+      else if (C.fixed_iter <= 0) {
+        const double rv = __longlong_as_double((long long)load_u64(&C.cur[rfin]));
+        if (!(rv < C.tol)) e |= 1;
+      }
+      if (e) atomicOr(err, e);
+    }
   }
 }
 

@@ -67,10 +67,15 @@ struct mm_ctx {
   int* d_idx;
   double *d_Ms, *d_kap, *d_aoms;
   double* d_M[3];
-  double *d_b[3], *d_d[3], *d_q, *d_hnew;
-  unsigned long long* d_res;  // 2 * nres slots
+  double *d_b[3], *d_d[3], *d_q;
+  unsigned char* d_nbm;       // neighbour masks of the evolving faces
+  void* A[3];                 // shadow H (ping-pong partner of H on magnetic faces)
+  unsigned long long* d_res;  // 2 control blocks of nres slots (slot 0: final count)
   int nres;
-  int coop_blocks;
+  unsigned int* d_bar;        // barrier state of hm_finish
+  int step_blocks, fin_blocks;
+  int* h_ring;                // pinned: final iteration count of recent sub-steps
+  int* d_ring;
   int* d_err;
 
   // iteration counts: one int per sub-step
@@ -101,6 +106,14 @@ struct mm_ctx {
 
   long step;
   int substep;
+
+  // adjoint support (see adjoint_host.h): checkpoints and the iterate log
+  double* hlog_cur;           // set while a forward recompute logs iterates
+  int hlog_cap;
+  bool adj_recompute;         // true while the adjoint recomputes a segment (no probes)
+  int ckpt_every;             // 0: adjoint disabled
+  std::vector<void*> ckpts;   // one device block per checkpoint
+  size_t ckpt_bytes;
 
   // optional kernel timing (mm_profile)
   bool prof;
@@ -339,6 +352,7 @@ mmk::Fields<T> make_fields(const mm_ctx* c) {
   for (int a = 0; a < 3; ++a) {
     F.E[a] = (T*)c->E[a];
     F.H[a] = (T*)c->H[a];
+    F.A[a] = (T*)c->A[a];
   }
   return F;
 }
@@ -355,7 +369,9 @@ mmk::Mag make_mag(const mm_ctx* c) {
     m.d[a] = c->d_d[a];
   }
   m.q = c->d_q;
-  m.hnew = c->d_hnew;
+  m.nbm = c->d_nbm;
+  m.hlog = c->hlog_cur;
+  m.hlog_cap = c->hlog_cap;
   m.off1 = c->off1;
   m.off2 = c->off2;
   m.n = c->nmag;
@@ -373,50 +389,72 @@ int kchunk_for(const mm_ctx* c, dim3& grid) {
   return kc;
 }
 
+// Number of iterations to enqueue as ordinary launches: one more than the
+// largest count seen in the last 64 sub-steps (read from pinned memory the
+// device writes; stale values are harmless because hm_finish completes any
+// iterations that were not enqueued).
+int iterations_to_enqueue(const mm_ctx* c) {
+  if (c->fixed_iter > 0) return c->fixed_iter;
+  int mx = 1;
+  for (int q = 0; q < 64; ++q) mx = std::max(mx, (int)((volatile int*)c->h_ring)[q]);
+  return std::max(1, std::min(std::min(mx + 1, 32), c->max_iter));
+}
+
 template <typename T>
 mm_status substep(mm_ctx* c) {
   Geo g = make_geo(c);
   mmk::Fields<T> F = make_fields<T>(c);
   const double h = 0.5 * c->dt;
   const double hmu0 = h / mmk::kMu0;
-  unsigned long long* res = c->d_res + (size_t)(c->substep & 1) * c->nres;
-  unsigned long long* res_next = c->d_res + (size_t)((c->substep + 1) & 1) * c->nres;
+  mmk::Ctl C;
+  C.cur = c->d_res + (size_t)(c->substep & 1) * c->nres;
+  C.next = c->d_res + (size_t)((c->substep + 1) & 1) * c->nres;
+  C.nres = c->nres;
+  C.tol = c->tol;
+  C.max_iter = c->max_iter;
+  C.fixed_iter = c->fixed_iter;
+  const double H0x = c->H0[0], H0y = c->H0[1], H0z = c->H0[2];
   if (c->nmag > 0) {
     mmk::Mag m = make_mag(c);
-    const int blocks = (c->nmag + 255) / 256;
     Timed tm(c, 2);
-    hipLaunchKernelGGL((mmk::hm_pre<T>), dim3(blocks), dim3(256), 0, c->stream, g, F, m, hmu0, c->H0[0],
-                       c->H0[1], c->H0[2], res + 1);
-    HIPCHECK(c, hipGetLastError());
+    hipLaunchKernelGGL((mmk::hm_pre<T>), dim3((c->nmag + 255) / 256), dim3(256), 0, c->stream, g, F, m, hmu0,
+                       H0x, H0y, H0z, C, c->d_err);
   }
+  HIPCHECK(c, hipGetLastError());
   dim3 grid;
   const int kc = kchunk_for(c, grid);
   {
-  Timed tm(c, 1);
-  if (c->mu)
-    hipLaunchKernelGGL((mmk::h_bulk<T, true>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->H[0], (T*)c->H[1],
-                       (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2], (const T*)c->mu,
-                       (T)hmu0, (T)h, kc);
-  else
-    hipLaunchKernelGGL((mmk::h_bulk<T, false>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->H[0], (T*)c->H[1],
-                       (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2], (const T*)c->mu,
-                       (T)hmu0, (T)h, kc);
+    Timed tm(c, 1);
+    if (c->mu)
+      hipLaunchKernelGGL((mmk::h_bulk<T, true>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->H[0], (T*)c->H[1],
+                         (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2], (const T*)c->mu,
+                         (T)hmu0, (T)h, kc);
+    else
+      hipLaunchKernelGGL((mmk::h_bulk<T, false>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->H[0], (T*)c->H[1],
+                         (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2], (const T*)c->mu,
+                         (T)hmu0, (T)h, kc);
   }
   HIPCHECK(c, hipGetLastError());
   if (c->nmag > 0) {
     mmk::Mag m = make_mag(c);
-    double H0x = c->H0[0], H0y = c->H0[1], H0z = c->H0[2];
-    int nres = c->nres;
-    double tol = c->tol;
-    int max_iter = c->max_iter, fixed_iter = c->fixed_iter;
-    int* iters_out = c->d_iters + c->substep;
-    int* err = c->d_err;
-    void* args[] = {(void*)&g,   (void*)&F,        (void*)&m,    (void*)&H0x,      (void*)&H0y,
-                    (void*)&H0z, (void*)&res,      (void*)&res_next, (void*)&nres, (void*)&tol,
-                    (void*)&max_iter, (void*)&fixed_iter, (void*)&iters_out, (void*)&err};
-    Timed tm(c, 3);
-    HIPCHECK(c, hipLaunchCooperativeKernel((const void*)&mmk::hm_iter<T>, dim3(c->coop_blocks), dim3(256), args,
-                                           0, c->stream));
+    const int R = iterations_to_enqueue(c);
+    for (int r = 2; r <= R; ++r) {
+      Timed tm(c, 3);
+      hipLaunchKernelGGL((mmk::hm_step<T>), dim3(c->step_blocks), dim3(256), 0, c->stream, g, F, m, H0x, H0y,
+                         H0z, C, r, c->d_err);
+    }
+    HIPCHECK(c, hipGetLastError());
+    {
+      Timed tm(c, 4);
+      hipLaunchKernelGGL((mmk::hm_finish<T>), dim3(c->fin_blocks), dim3(256), 0, c->stream, g, F, m, H0x, H0y,
+                         H0z, C, R + 1, c->d_bar, c->d_err);
+    }
+    {
+      Timed tm(c, 6);
+      hipLaunchKernelGGL((mmk::hm_commit<T>), dim3(c->step_blocks), dim3(256), 0, c->stream, F, m, C,
+                         c->d_iters + c->substep, c->d_ring + (c->substep & 63), c->d_err);
+    }
+    HIPCHECK(c, hipGetLastError());
   }
   c->substep++;
   return MM_OK;
@@ -484,6 +522,10 @@ mm_status read_sticky(mm_ctx* c) {
 mm_status take_sticky(mm_ctx* c) {
   const int w = c->sticky;
   c->sticky = 0;
+  if (w & 4) {
+    (void)hipMemset(c->d_bar, 0, 2 * sizeof(unsigned int));
+    return fail(c, MM_EDEVICE, "the sub-step completion barrier timed out");
+  }
   if (w & 2) return fail(c, MM_ENONFINITE, "a sub-step residual was not finite");
   if (w & 1) return fail(c, MM_ENOCONV, "a sub-step reached max_iter without meeting tol");
   return MM_OK;
@@ -633,9 +675,48 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
       if (!c->d_M[a] || !c->d_b[a] || !c->d_d[a]) return fail(c, MM_ENOMEM, "magnetic-face allocation failed");
     }
     c->d_q = (double*)dalloc(c, ntot * sizeof(double));
-    c->d_hnew = (double*)dalloc(c, ntot * sizeof(double));
-    if (!c->d_idx || !c->d_Ms || !c->d_kap || !c->d_aoms || !c->d_q || !c->d_hnew)
+    c->d_nbm = (unsigned char*)dalloc(c, ntot);
+    if (!c->d_idx || !c->d_Ms || !c->d_kap || !c->d_aoms || !c->d_q || !c->d_nbm)
       return fail(c, MM_ENOMEM, "magnetic-face allocation failed");
+    for (int a = 0; a < 3; ++a) {
+      c->A[a] = dalloc(c, c->nelem * c->esz);
+      if (!c->A[a]) return fail(c, MM_ENOMEM, "allocation of the shadow H failed");
+      HIPCHECK(c, hipMemsetAsync(c->A[a], 0, c->nelem * c->esz, c->stream));
+    }
+    // neighbour masks: bit q set when transverse neighbour q (numbered as in
+    // mmk::h_eff) is an evolving magnetic face
+    {
+      std::vector<std::vector<bool>> ev(3, std::vector<bool>(c->nelem, false));
+      for (size_t t = 0; t < (size_t)c->nmag; ++t) ev[c->h_fam[t]][c->h_idx[t]] = true;
+      std::vector<unsigned char> nbm(ntot, 0);
+      auto dn = [&](int i, int n, bool p) { return (p && i == 0) ? n - 1 : i - 1; };
+      auto up = [&](int i, int n, bool p) { return (p && i == n - 1) ? 0 : i + 1; };
+      const bool pxp = c->per & 1, pyp = c->per & 2, pzp = c->per & 4;
+      for (size_t t = 0; t < (size_t)c->nmag; ++t) {
+        const int pi = c->h_idx[t], f = c->h_fam[t];
+        const int k = pi / (c->px * c->py), rr = pi - k * c->px * c->py, j = rr / c->px, i = rr - j * c->px;
+        int comp[8], ii[8], jj[8], kk[8];
+        auto set = [&](int q, int cp, int a, int b2, int d2) { comp[q] = cp; ii[q] = a; jj[q] = b2; kk[q] = d2; };
+        if (f == 0) {
+          const int im = dn(i, c->nx, pxp), jp = up(j, c->ny, pyp), kp = up(k, c->nz, pzp);
+          set(0, 1, im, j, k); set(1, 1, i, j, k); set(2, 1, im, jp, k); set(3, 1, i, jp, k);
+          set(4, 2, im, j, k); set(5, 2, i, j, k); set(6, 2, im, j, kp); set(7, 2, i, j, kp);
+        } else if (f == 1) {
+          const int jm = dn(j, c->ny, pyp), ip = up(i, c->nx, pxp), kp = up(k, c->nz, pzp);
+          set(0, 0, i, jm, k); set(1, 0, i, j, k); set(2, 0, ip, jm, k); set(3, 0, ip, j, k);
+          set(4, 2, i, jm, k); set(5, 2, i, j, k); set(6, 2, i, jm, kp); set(7, 2, i, j, kp);
+        } else {
+          const int km = dn(k, c->nz, pzp), ip = up(i, c->nx, pxp), jp = up(j, c->ny, pyp);
+          set(0, 0, i, j, km); set(1, 0, i, j, k); set(2, 0, ip, j, km); set(3, 0, ip, j, k);
+          set(4, 1, i, j, km); set(5, 1, i, j, k); set(6, 1, i, jp, km); set(7, 1, i, jp, k);
+        }
+        unsigned char mk = 0;
+        for (int q = 0; q < 8; ++q)
+          if (ev[comp[q]][pidx(c, ii[q], jj[q], kk[q])]) mk |= (unsigned char)(1u << q);
+        nbm[t] = mk;
+      }
+      HIPCHECK(c, hipMemcpy(c->d_nbm, nbm.data(), ntot, hipMemcpyHostToDevice));
+    }
     HIPCHECK(c, hipMemcpy(c->d_idx, c->h_idx.data(), ntot * sizeof(int), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(c->d_Ms, hv[0].data(), ntot * sizeof(double), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(c->d_kap, hv[1].data(), ntot * sizeof(double), hipMemcpyHostToDevice));
@@ -643,22 +724,24 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
     for (int a = 0; a < 3; ++a)
       HIPCHECK(c, hipMemcpy(c->d_M[a], hv[3 + a].data(), ntot * sizeof(double), hipMemcpyHostToDevice));
   }
-  c->nres = std::max(c->max_iter, c->fixed_iter) + 1;
+  c->nres = std::max(c->max_iter, c->fixed_iter) + 2;
   c->d_res = (unsigned long long*)dalloc(c, 2 * (size_t)c->nres * sizeof(unsigned long long));
   c->d_err = (int*)dalloc(c, sizeof(int));
-  if (!c->d_res || !c->d_err) return fail(c, MM_ENOMEM, "allocation failed");
+  c->d_bar = (unsigned int*)dalloc(c, 2 * sizeof(unsigned int));
+  if (!c->d_res || !c->d_err || !c->d_bar) return fail(c, MM_ENOMEM, "allocation failed");
   HIPCHECK(c, hipMemset(c->d_res, 0, 2 * (size_t)c->nres * sizeof(unsigned long long)));
   HIPCHECK(c, hipMemset(c->d_err, 0, sizeof(int)));
+  HIPCHECK(c, hipMemset(c->d_bar, 0, 2 * sizeof(unsigned int)));
+  HIPCHECK(c, hipHostMalloc((void**)&c->h_ring, 64 * sizeof(int), hipHostMallocMapped));
+  std::memset(c->h_ring, 0, 64 * sizeof(int));
+  HIPCHECK(c, hipHostGetDevicePointer((void**)&c->d_ring, c->h_ring, 0));
   if (c->nmag > 0) {
-    int per_cu = 0;
-    HIPCHECK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, fp32 ? (const void*)&mmk::hm_iter<float> : (const void*)&mmk::hm_iter<double>, 256, 0));
     int dev = 0, ncu = 0;
     HIPCHECK(c, hipGetDevice(&dev));
     HIPCHECK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     const int want = (c->nmag + 255) / 256;
-    c->coop_blocks = std::max(1, std::min(want, per_cu * ncu));
-    if (per_cu < 1) return fail(c, MM_EDEVICE, "the iteration kernel cannot be made resident");
+    c->step_blocks = std::max(1, std::min(want, 8 * ncu));
+    c->fin_blocks = std::max(1, std::min(want, ncu));
   }
 
   // soft source: J0 p over the bounding box of its nonzero interior edges
@@ -715,6 +798,10 @@ void release(mm_ctx* c) {
     (void)hipEventDestroy(pr.second);
   }
   c->ev_pool.clear();
+  if (c->h_ring) {
+    (void)hipHostFree(c->h_ring);
+    c->h_ring = nullptr;
+  }
   while (!c->allocs.empty()) dfree(c, c->allocs.back().first);
 }
 

@@ -72,6 +72,16 @@ def test_filter_crop_short_run():
     PU.compare(ref, sim, ref0, TOL64)
 
 
+def test_iterations_beyond_the_enqueued_launches():
+    """A tight tolerance needs more iterations than the launches enqueued from
+    the recent history, so hm_finish completes them (its barrier path)."""
+    cfg = PU.with_random_start(W.slab64(steps=6), seed=12, amp_e=3e6, amp_h=5e4)
+    cfg.tol = 1e-15
+    ref, sim, ref0 = PU.run_pair(cfg, cfg.steps)
+    PU.compare(ref, sim, ref0, TOL64)
+    assert max(ref.iters) >= 4
+
+
 def test_fixed_iteration_mode_matches():
     cfg = PU.with_random_start(W.slab64(steps=10), seed=6, amp_e=1e6, amp_h=2e4)
     ref, sim, ref0 = PU.run_pair(cfg, cfg.steps, fixed_iter=2)

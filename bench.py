@@ -82,6 +82,37 @@ def run_gpu(cfg, precision, steps, warmup):
     return sim, info, ms, wall, kern, iters
 
 
+def run_adjoint_cost(steps=4000, ckpt=100):
+    """Forward time of the 128x64x64 design grid (smooth random eps_r, Ms) over
+    `steps` steps with checkpoints, then the time of mm_adjoint (segment
+    recompute + reverse sweep) for the gradient of the integrated flux."""
+    import torch
+    import paper_2103_12819_amd as mm
+
+    cfg = W.design128(seed=0, steps=steps)
+    sim = mm.from_config(cfg)
+    sim.enable_adjoint(ckpt)
+    sim.step(5)          # warm-up of the launch path (part of the differentiated run)
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.step(steps - 5)
+    sim.sync()
+    t_fwd = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    ge, gm = sim.adjoint(0)
+    t_adj = time.perf_counter() - t1
+    _, L = sim.probe(0)
+    sim.close()
+    torch.cuda.synchronize()
+    per_fwd = t_fwd / (steps - 5)
+    return {"workload": f"design128 128x64x64, {steps} steps, checkpoints every {ckpt}",
+            "forward_ms_per_step": round(per_fwd * 1e3, 4),
+            "adjoint_ms_per_step": round(t_adj / steps * 1e3, 4),
+            "adjoint_over_forward": round((t_adj / steps) / per_fwd, 3),
+            "loss": L, "max_abs_grad_eps_r": float(np.abs(ge).max()),
+            "max_abs_grad_Ms": float(np.abs(gm).max())}
+
+
 def cpu_baseline(budget_s=15.0):
     """The oracle on the 128x64x64 crop of the same grid, as many steps as fit
     in the time budget (at least 2)."""
@@ -112,6 +143,7 @@ def main():
     ap.add_argument("--workload", default="filter512")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -188,6 +220,10 @@ def main():
         print(f"[bench] fp32 {ms32 / args.steps:.3f} ms/step, {v32:.1f} Mcell/s", flush=True)
         sim32.close()
     sim64.close()
+    if not args.no_adjoint:
+        print("[bench] adjoint cost (design128)", flush=True)
+        out["adjoint"] = run_adjoint_cost()
+        print(f"[bench] adjoint {out['adjoint']}", flush=True)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", flush=True)
         out["cpu_baseline"] = cpu_baseline()

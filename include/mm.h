@@ -164,6 +164,24 @@ mm_status mm_sync(mm_ctx *c);
  * device bytes held by the context. */
 mm_status mm_info(const mm_ctx *c, int64_t out[8]);
 
+/* Adjoint (an addition to the paper's method).  mm_adjoint_enable, called
+ * before the first step, makes mm_step save the state (E, H, M) every
+ * `checkpoint_every` steps (device memory held by the context).
+ * mm_adjoint then returns, in host arrays of nx*ny*nz doubles (cell maps,
+ * x fastest), the gradient of L = sum_{n=1}^{N} dt P^n -- the
+ * time-integrated value of flux probe `probe_id` over the N steps taken --
+ * with respect to the eps_r and Ms cell maps.  It is the exact reverse of
+ * the computation (same iteration counts; the sub-step iterates are
+ * replayed), through the 4-cell edge mean of eps_r and, for Ms, the face
+ * mean Ms_f (renormalisation target, alpha/Ms, initial M).  Which faces
+ * are magnetic is held fixed: cells with Ms = 0 get 0.  It recomputes each
+ * segment from its checkpoint and leaves the context's state, step count
+ * and probes as they were.  Requirements: mu_r = 1 everywhere (MM_EINVAL
+ * from mm_adjoint_enable otherwise), a flux probe, at most 16 iterations
+ * per sub-step (MM_ESTATE otherwise).  Synchronises the stream. */
+mm_status mm_adjoint_enable(mm_ctx *c, int32_t checkpoint_every);
+mm_status mm_adjoint(mm_ctx *c, int32_t probe_id, double *grad_eps_r, double *grad_Ms);
+
 /* Kernel timing.  mm_profile(c, 1) makes every later mm_step bracket each
  * kernel launch with a pair of HIP events on the context's stream (class
  * 0 e_update, 1 h_bulk, 2 hm_pre, 3 hm_step, 4 hm_finish, 5 probes,

@@ -193,6 +193,19 @@ class Sim:
         keys = ["n_mag", "n_wall_mag", "n_src", "px", "py", "pz", "elem_bytes", "device_bytes"]
         return dict(zip(keys, list(out)))
 
+    def enable_adjoint(self, checkpoint_every=100):
+        """Save checkpoints while stepping so that adjoint() can run (before the first step)."""
+        self._check(self._lib.mm_adjoint_enable(self._ctx, int(checkpoint_every)))
+
+    def adjoint(self, probe_id):
+        """Gradients (d L/d eps_r, d L/d Ms) as host-layout cell maps, where L is
+        the time integral of flux probe `probe_id` over all steps taken."""
+        shp = (self.n[2], self.n[1], self.n[0])
+        ge = np.zeros(shp)
+        gm = np.zeros(shp)
+        self._check(self._lib.mm_adjoint(self._ctx, int(probe_id), _dp(ge), _dp(gm)))
+        return ge, gm
+
     KERNEL_CLASSES = ["e_update", "h_bulk", "hm_pre", "hm_step", "hm_finish", "probes", "hm_commit"]
 
     def profile(self, enable=True):
@@ -234,3 +247,55 @@ def from_config(cfg, precision="fp64", fixed_iter=0, with_probes=True, **kw):
         for p in cfg.probes:
             sim.add_probe(p.kind, p.field, p.i, p.j, p.k)
     return sim
+
+
+class FluxLoss:
+    """torch.autograd.Function for L(eps_r, Ms) = time-integrated Poynting flux
+    through a probe plane after `steps` steps of a workload.
+
+        L = FluxLoss.apply(eps_r, Ms, cfg, steps, probe_id, precision, checkpoint_every)
+
+    eps_r and Ms are host-layout (nz, ny, nx) float64 tensors (any device);
+    every other input of `cfg` (a workloads.Config) is held fixed.  The forward
+    runs the HIP path; backward calls mm_adjoint (reverse sweep with
+    checkpoint-and-recompute) and scales the gradients by dL.
+    """
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, *args):
+        if cls._fn is None:
+            cls._fn = _make_flux_loss()
+        return cls._fn.apply(*args)
+
+
+def _make_flux_loss():
+    import torch
+
+    class _FluxLossFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, eps_r, Ms, cfg, steps, probe_id, precision="fp64", checkpoint_every=100):
+            import copy
+            c2 = copy.copy(cfg)
+            c2.eps_r = eps_r.detach().to("cpu", torch.float64).numpy()
+            c2.Ms = Ms.detach().to("cpu", torch.float64).numpy()
+            sim = from_config(c2, precision=precision)
+            sim.enable_adjoint(checkpoint_every)
+            sim.step(int(steps))
+            _, L = sim.probe(int(probe_id))
+            ctx.sim = sim
+            ctx.probe_id = int(probe_id)
+            ctx.devices = (eps_r.device, Ms.device)
+            return torch.tensor(L, dtype=torch.float64, device=eps_r.device)
+
+        @staticmethod
+        def backward(ctx, dL):
+            ge, gm = ctx.sim.adjoint(ctx.probe_id)
+            ctx.sim.close()
+            s = float(dL)
+            g_eps = torch.from_numpy(ge * s).to(ctx.devices[0])
+            g_ms = torch.from_numpy(gm * s).to(ctx.devices[1])
+            return g_eps, g_ms, None, None, None, None, None
+
+    return _FluxLossFn

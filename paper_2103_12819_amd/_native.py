@@ -14,8 +14,8 @@ MM_BC_PEC, MM_BC_PERIODIC = 0, 1
 MM_FP64, MM_FP32 = 0, 1
 
 EXPORTED = ["mm_init", "mm_step", "mm_add_probe", "mm_probe", "mm_get_field", "mm_set_field",
-            "mm_stats", "mm_sync", "mm_info", "mm_profile", "mm_profile_read", "mm_last_error",
-            "mm_destroy"]
+            "mm_stats", "mm_sync", "mm_info", "mm_adjoint_enable", "mm_adjoint", "mm_profile",
+            "mm_profile_read", "mm_last_error", "mm_destroy"]
 
 _dptr = C.POINTER(C.c_double)
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -83,6 +83,10 @@ def load(path: str = LIB_PATH):
     lib.mm_sync.restype = C.c_int
     lib.mm_info.argtypes = [P, C.POINTER(C.c_int64)]
     lib.mm_info.restype = C.c_int
+    lib.mm_adjoint_enable.argtypes = [P, C.c_int32]
+    lib.mm_adjoint_enable.restype = C.c_int
+    lib.mm_adjoint.argtypes = [P, C.c_int32, _dptr, _dptr]
+    lib.mm_adjoint.restype = C.c_int
     lib.mm_profile.argtypes = [P, C.c_int32]
     lib.mm_profile.restype = C.c_int
     lib.mm_profile_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]

@@ -1,0 +1,480 @@
+// Host side of the adjoint (included by mm.hip inside its anonymous
+// namespace, after the forward runtime).
+//
+// Forward: with mm_adjoint_enable(c, K), mm_step saves the state (E, H, M)
+// at every step index that is a multiple of K.
+// mm_adjoint: for each K-step segment, last first, restore its checkpoint
+// and recompute the segment, storing per step E^n, H^n, M^n, H^{n+1/2},
+// M^{n+1/2} and the H iterates of both sub-steps; then reverse the steps
+// (flux seed at n+1, Step 3, Step 2, Step 1) with the kernels of adjoint.h.
+// Finally map the edge-eps and face-Ms cotangents to the cell maps on the
+// host and put the final state back.
+
+struct AdjWork {
+  int K = 0;
+  int cap = 0;                 // iterate-log slots per sub-step
+  void* Eb[3] = {};
+  void* Hb[3] = {};
+  void* Xb[3] = {};
+  void* Gb[3] = {};
+  void* W[3] = {};
+  double* Q[9] = {};
+  double** dQ = nullptr;
+  double* epsb[3] = {};
+  std::vector<void*> sE, sH, sHh;
+  std::vector<double*> sM, sMh, slog;
+  double *b[3] = {}, *d[3] = {}, *hes[3] = {}, *bb[3] = {}, *db[3] = {}, *Mb[3] = {};
+  double *qb = nullptr, *hbit = nullptr, *msf_b = nullptr, *aoms_b = nullptr;
+  int* tidx = nullptr;
+  unsigned char* tfam = nullptr;
+  int* tmag = nullptr;
+  int nt = 0;
+  void* fin = nullptr;
+};
+
+size_t state_bytes(const mm_ctx* c) {
+  return 6 * c->nelem * c->esz + 3 * (c->h_idx.size() ? c->h_idx.size() : 1) * sizeof(double);
+}
+
+// state block layout: E0 E1 E2 H0 H1 H2 (nelem * esz each), M0 M1 M2 (ntot doubles each)
+mm_status copy_state(mm_ctx* c, void* blk, bool save) {
+  const size_t fb = c->nelem * c->esz;
+  const size_t ntot = c->h_idx.size();
+  char* p = (char*)blk;
+  for (int a = 0; a < 3; ++a) {
+    void* e = p + a * fb;
+    void* h = p + (3 + a) * fb;
+    HIPCHECK(c, hipMemcpyAsync(save ? e : c->E[a], save ? c->E[a] : e, fb, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(save ? h : c->H[a], save ? c->H[a] : h, fb, hipMemcpyDeviceToDevice, c->stream));
+  }
+  if (ntot)
+    for (int a = 0; a < 3; ++a) {
+      void* m = p + 6 * fb + a * ntot * sizeof(double);
+      HIPCHECK(c, hipMemcpyAsync(save ? m : (void*)c->d_M[a], save ? (void*)c->d_M[a] : m, ntot * sizeof(double),
+                                 hipMemcpyDeviceToDevice, c->stream));
+    }
+  return MM_OK;
+}
+
+mm_status save_checkpoint(mm_ctx* c, size_t idx) {
+  while (c->ckpts.size() <= idx) {
+    void* blk = dalloc(c, state_bytes(c));
+    if (!blk) return fail(c, MM_ENOMEM, "checkpoint allocation failed");
+    c->ckpts.push_back(blk);
+  }
+  return copy_state(c, c->ckpts[idx], true);
+}
+
+// copy 3 field arrays (E or H) to / from a packed block of 3 arrays
+mm_status copy3(mm_ctx* c, void* blk, void* const* arr, bool save) {
+  const size_t fb = c->nelem * c->esz;
+  for (int a = 0; a < 3; ++a) {
+    void* q = (char*)blk + a * fb;
+    HIPCHECK(c, hipMemcpyAsync(save ? q : arr[a], save ? arr[a] : q, fb, hipMemcpyDeviceToDevice, c->stream));
+  }
+  return MM_OK;
+}
+
+mm_status copyM(mm_ctx* c, double* blk, bool save) {
+  const size_t ntot = c->h_idx.size();
+  for (int a = 0; a < 3 && ntot; ++a)
+    HIPCHECK(c, hipMemcpyAsync(save ? (void*)(blk + a * ntot) : (void*)c->d_M[a],
+                               save ? (void*)c->d_M[a] : (void*)(blk + a * ntot), ntot * sizeof(double),
+                               hipMemcpyDeviceToDevice, c->stream));
+  return MM_OK;
+}
+
+// Faces that evolving magnetic faces read (themselves and their 8
+// transverse neighbours), each once, with its compact index when it is an
+// evolving magnetic face (-1 otherwise).
+void touched_faces(const mm_ctx* c, std::vector<int>& idx, std::vector<unsigned char>& fam, std::vector<int>& mag) {
+  std::unordered_map<long long, int> evolving;
+  std::unordered_set<long long> done;
+  auto key = [&](int f, int pi) { return (long long)f * (long long)c->nelem + pi; };
+  for (int t = 0; t < c->nmag; ++t) evolving[key(c->h_fam[t], c->h_idx[t])] = t;
+  auto dn = [&](int i, int n, bool p) { return (p && i == 0) ? n - 1 : i - 1; };
+  auto up = [&](int i, int n, bool p) { return (p && i == n - 1) ? 0 : i + 1; };
+  const bool pxp = c->per & 1, pyp = c->per & 2, pzp = c->per & 4;
+  auto add = [&](int f, int pi) {
+    const long long kk = key(f, pi);
+    if (!done.insert(kk).second) return;
+    idx.push_back(pi);
+    fam.push_back((unsigned char)f);
+    auto it = evolving.find(kk);
+    mag.push_back(it == evolving.end() ? -1 : it->second);
+  };
+  for (int t = 0; t < c->nmag; ++t) {
+    const int pi = c->h_idx[t], f = c->h_fam[t];
+    const int k = pi / (c->px * c->py), rr = pi - k * c->px * c->py, j = rr / c->px, i = rr - j * c->px;
+    auto P = [&](int a, int b2, int d2) { return (int)pidx(c, a, b2, d2); };
+    add(f, pi);
+    if (f == 0) {
+      const int im = dn(i, c->nx, pxp), jp = up(j, c->ny, pyp), kp = up(k, c->nz, pzp);
+      add(1, P(im, j, k)); add(1, P(i, j, k)); add(1, P(im, jp, k)); add(1, P(i, jp, k));
+      add(2, P(im, j, k)); add(2, P(i, j, k)); add(2, P(im, j, kp)); add(2, P(i, j, kp));
+    } else if (f == 1) {
+      const int jm = dn(j, c->ny, pyp), ip = up(i, c->nx, pxp), kp = up(k, c->nz, pzp);
+      add(0, P(i, jm, k)); add(0, P(i, j, k)); add(0, P(ip, jm, k)); add(0, P(ip, j, k));
+      add(2, P(i, jm, k)); add(2, P(i, j, k)); add(2, P(i, jm, kp)); add(2, P(i, j, kp));
+    } else {
+      const int km = dn(k, c->nz, pzp), ip = up(i, c->nx, pxp), jp = up(j, c->ny, pyp);
+      add(0, P(i, j, km)); add(0, P(i, j, k)); add(0, P(ip, j, km)); add(0, P(ip, j, k));
+      add(1, P(i, j, km)); add(1, P(i, j, k)); add(1, P(i, jp, km)); add(1, P(i, jp, k));
+    }
+  }
+}
+
+mm_status adj_alloc(mm_ctx* c) {
+  if (c->adjw && c->adjw->K == c->ckpt_every) return MM_OK;
+  AdjWork* w = new AdjWork();
+  c->adjw = w;
+  w->K = c->ckpt_every;
+  w->cap = std::min(std::max(c->max_iter, c->fixed_iter), 16);
+  c->hlog_cap = w->cap;
+  const size_t fb = c->nelem * c->esz, fd = c->nelem * sizeof(double);
+  auto need = [&](void* p) { return p != nullptr; };
+  for (int a = 0; a < 3; ++a) {
+    w->Eb[a] = dalloc(c, fb);
+    w->Hb[a] = dalloc(c, fb);
+    w->Xb[a] = dalloc(c, fb);
+    w->Gb[a] = dalloc(c, fb);
+    w->W[a] = dalloc(c, fb);
+    w->epsb[a] = (double*)dalloc(c, fd);
+    if (!need(w->Eb[a]) || !need(w->Hb[a]) || !need(w->Xb[a]) || !need(w->Gb[a]) || !need(w->W[a]) ||
+        !need(w->epsb[a]))
+      return fail(c, MM_ENOMEM, "adjoint work allocation failed");
+    for (void* p : {w->Xb[a], w->Gb[a], w->W[a]}) HIPCHECK(c, hipMemsetAsync(p, 0, fb, c->stream));
+  }
+  const size_t nm = (size_t)std::max(c->nmag, 1);
+  const size_t ntot = std::max<size_t>(c->h_idx.size(), 1);
+  if (c->nmag > 0) {
+    for (int q = 0; q < 9; ++q) {
+      w->Q[q] = (double*)dalloc(c, fd);
+      if (!w->Q[q]) return fail(c, MM_ENOMEM, "adjoint work allocation failed");
+      HIPCHECK(c, hipMemsetAsync(w->Q[q], 0, fd, c->stream));
+    }
+    w->dQ = (double**)dalloc(c, 9 * sizeof(double*));
+    if (!w->dQ) return fail(c, MM_ENOMEM, "adjoint work allocation failed");
+    HIPCHECK(c, hipMemcpy(w->dQ, w->Q, 9 * sizeof(double*), hipMemcpyHostToDevice));
+    for (int a = 0; a < 3; ++a) {
+      w->b[a] = (double*)dalloc(c, nm * 8);
+      w->d[a] = (double*)dalloc(c, nm * 8);
+      w->hes[a] = (double*)dalloc(c, nm * 8);
+      w->bb[a] = (double*)dalloc(c, nm * 8);
+      w->db[a] = (double*)dalloc(c, nm * 8);
+      w->Mb[a] = (double*)dalloc(c, ntot * 8);
+      if (!w->b[a] || !w->d[a] || !w->hes[a] || !w->bb[a] || !w->db[a] || !w->Mb[a])
+        return fail(c, MM_ENOMEM, "adjoint work allocation failed");
+    }
+    w->qb = (double*)dalloc(c, nm * 8);
+    w->hbit = (double*)dalloc(c, nm * 8);
+    w->msf_b = (double*)dalloc(c, nm * 8);
+    w->aoms_b = (double*)dalloc(c, nm * 8);
+    if (!w->qb || !w->hbit || !w->msf_b || !w->aoms_b) return fail(c, MM_ENOMEM, "adjoint work allocation failed");
+    std::vector<int> ti, tm;
+    std::vector<unsigned char> tf;
+    touched_faces(c, ti, tf, tm);
+    w->nt = (int)ti.size();
+    w->tidx = (int*)dalloc(c, ti.size() * 4);
+    w->tfam = (unsigned char*)dalloc(c, tf.size());
+    w->tmag = (int*)dalloc(c, tm.size() * 4);
+    if (!w->tidx || !w->tfam || !w->tmag) return fail(c, MM_ENOMEM, "adjoint work allocation failed");
+    HIPCHECK(c, hipMemcpy(w->tidx, ti.data(), ti.size() * 4, hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(w->tfam, tf.data(), tf.size(), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(w->tmag, tm.data(), tm.size() * 4, hipMemcpyHostToDevice));
+  }
+  for (int j = 0; j < w->K; ++j) {
+    void* e = dalloc(c, 3 * fb);
+    void* h = dalloc(c, 3 * fb);
+    void* hh = dalloc(c, 3 * fb);
+    double* m = (double*)dalloc(c, 3 * ntot * 8);
+    double* mh = (double*)dalloc(c, 3 * ntot * 8);
+    double* lg = (double*)dalloc(c, 2 * (size_t)w->cap * nm * 8);
+    if (!e || !h || !hh || !m || !mh || !lg) return fail(c, MM_ENOMEM, "adjoint segment storage allocation failed");
+    w->sE.push_back(e);
+    w->sH.push_back(h);
+    w->sHh.push_back(hh);
+    w->sM.push_back(m);
+    w->sMh.push_back(mh);
+    w->slog.push_back(lg);
+  }
+  w->fin = dalloc(c, state_bytes(c));
+  if (!w->fin) return fail(c, MM_ENOMEM, "adjoint work allocation failed");
+  return MM_OK;
+}
+
+mmk::AdjMag make_adjmag(const mm_ctx* c, const double* Ms0blk, const double* log) {
+  const AdjWork& w = *c->adjw;
+  const size_t ntot = c->h_idx.size();
+  mmk::AdjMag a;
+  a.idx = c->d_idx;
+  a.nbm = c->d_nbm;
+  a.Ms = c->d_Ms;
+  a.kap = c->d_kap;
+  a.aoms = c->d_aoms;
+  for (int q = 0; q < 3; ++q) {
+    a.Ms0[q] = Ms0blk + q * ntot;
+    a.b[q] = w.b[q];
+    a.d[q] = w.d[q];
+    a.hes[q] = w.hes[q];
+    a.bb[q] = w.bb[q];
+    a.db[q] = w.db[q];
+    a.Mb[q] = w.Mb[q];
+  }
+  a.hlog = log;
+  a.qb = w.qb;
+  a.hbit = w.hbit;
+  a.msf_b = w.msf_b;
+  a.aoms_b = w.aoms_b;
+  a.off1 = c->off1;
+  a.off2 = c->off2;
+  a.n = c->nmag;
+  return a;
+}
+
+template <typename T>
+T* arr3(const void* blk, const mm_ctx* c, int a) {
+  return (T*)((char*)blk + (size_t)a * c->nelem * c->esz);
+}
+
+// Reverse of one H-M sub-step whose input was (Hs, Ms0), output H (Ho),
+// iterates `log` and count R.
+template <typename T>
+mm_status adj_substep(mm_ctx* c, T* const* Hs, const double* Ms0, T* const* Ho, const double* log, int R) {
+  AdjWork& w = *c->adjw;
+  Geo g = make_geo(c);
+  T* Eb[3] = {(T*)w.Eb[0], (T*)w.Eb[1], (T*)w.Eb[2]};
+  T* Hb[3] = {(T*)w.Hb[0], (T*)w.Hb[1], (T*)w.Hb[2]};
+  T* Xb[3] = {(T*)w.Xb[0], (T*)w.Xb[1], (T*)w.Xb[2]};
+  T* Gb[3] = {(T*)w.Gb[0], (T*)w.Gb[1], (T*)w.Gb[2]};
+  T* Wv[3] = {(T*)w.W[0], (T*)w.W[1], (T*)w.W[2]};
+  const double H0x = c->H0[0], H0y = c->H0[1], H0z = c->H0[2];
+  if (c->nmag > 0) {
+    mmk::AdjMag a = make_adjmag(c, Ms0, log);
+    const int nb = (c->nmag + 255) / 256, tb = (w.nt + 255) / 256;
+    hipLaunchKernelGGL((mmk::adj_mag_prep<T>), dim3(nb), dim3(256), 0, c->stream, g, Hs[0], Hs[1], Hs[2], a, H0x,
+                       H0y, H0z);
+    for (int r = R; r >= 1; --r) {
+      if (r >= 2)
+        hipLaunchKernelGGL((mmk::adj_scatter_iter<T>), dim3(nb), dim3(256), 0, c->stream, a, Wv[0], Wv[1], Wv[2],
+                           r - 1);
+      hipLaunchKernelGGL((mmk::adj_mag_iter<T>), dim3(nb), dim3(256), 0, c->stream, g, a, Hs[0], Hs[1], Hs[2],
+                         Ho[0], Ho[1], Ho[2], Wv[0], Wv[1], Wv[2], Hb[0], Hb[1], Hb[2], w.dQ, r, R, H0x, H0y,
+                         H0z);
+      hipLaunchKernelGGL((mmk::adj_gather<T>), dim3(tb), dim3(256), 0, c->stream, g, w.tidx, w.tfam, w.tmag, w.nt,
+                         w.dQ, a, Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], r >= 2 ? 0 : 1);
+    }
+    hipLaunchKernelGGL((mmk::adj_mag_inv<T>), dim3(nb), dim3(256), 0, c->stream, a, Xb[0], Xb[1], Xb[2], w.dQ);
+    hipLaunchKernelGGL((mmk::adj_gather<T>), dim3(tb), dim3(256), 0, c->stream, g, w.tidx, w.tfam, w.tmag, w.nt,
+                       w.dQ, a, Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], 1);
+    HIPCHECK(c, hipGetLastError());
+  }
+  const dim3 fgrid((c->nx + 63) / 64, (c->ny + 3) / 4, c->nz);
+  hipLaunchKernelGGL((mmk::adj_face_pass<T>), fgrid, dim3(64, 4), 0, c->stream, g, Hb[0], Hb[1], Hb[2], Xb[0],
+                     Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], Wv[0], Wv[1], Wv[2], 0.5 * c->dt / mmk::kMu0);
+  dim3 grid;
+  const int kc = kchunk_for(c, grid);
+  hipLaunchKernelGGL((mmk::add_curl_h<T>), grid, dim3(64, 4), 0, c->stream, g, Eb[0], Eb[1], Eb[2], Wv[0], Wv[1],
+                     Wv[2], kc);
+  if (c->nmag > 0)
+    hipLaunchKernelGGL((mmk::zero_touched<T>), dim3((w.nt + 255) / 256), dim3(256), 0, c->stream, w.tidx, w.tfam,
+                       w.nt, Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2]);
+  HIPCHECK(c, hipGetLastError());
+  return MM_OK;
+}
+
+// Reverse of Step 2 of step c->step: En = E^n, Hh = H^{n+1/2}.
+template <typename T>
+mm_status adj_estep(mm_ctx* c, const void* En, const void* Hh) {
+  AdjWork& w = *c->adjw;
+  Geo g = make_geo(c);
+  dim3 grid;
+  const int kc = kchunk_for(c, grid);
+  const mmk::Src src = make_src(c);
+  T* Eb[3] = {(T*)w.Eb[0], (T*)w.Eb[1], (T*)w.Eb[2]};
+  T* Hb[3] = {(T*)w.Hb[0], (T*)w.Hb[1], (T*)w.Hb[2]};
+  T* Wv[3] = {(T*)w.W[0], (T*)w.W[1], (T*)w.W[2]};
+  if (c->sig)
+    hipLaunchKernelGGL((mmk::adj_e_coef<T, true>), grid, dim3(64, 4), 0, c->stream, g, Eb[0], Eb[1], Eb[2],
+                       arr3<T>(En, c, 0), arr3<T>(En, c, 1), arr3<T>(En, c, 2), arr3<T>(Hh, c, 0),
+                       arr3<T>(Hh, c, 1), arr3<T>(Hh, c, 2), (const T*)c->eps, (const T*)c->sig, Wv[0], Wv[1],
+                       Wv[2], w.epsb[0], w.epsb[1], w.epsb[2], (T)c->dt, src, kc);
+  else
+    hipLaunchKernelGGL((mmk::adj_e_coef<T, false>), grid, dim3(64, 4), 0, c->stream, g, Eb[0], Eb[1], Eb[2],
+                       arr3<T>(En, c, 0), arr3<T>(En, c, 1), arr3<T>(En, c, 2), arr3<T>(Hh, c, 0),
+                       arr3<T>(Hh, c, 1), arr3<T>(Hh, c, 2), (const T*)c->eps, (const T*)c->sig, Wv[0], Wv[1],
+                       Wv[2], w.epsb[0], w.epsb[1], w.epsb[2], (T)c->dt, src, kc);
+  // H_bar += curl E(W): the non-magnetic H kernel with coefficient -1
+  hipLaunchKernelGGL((mmk::h_bulk<T, false>), grid, dim3(64, 4), 0, c->stream, g, Hb[0], Hb[1], Hb[2],
+                     (const T*)Wv[0], (const T*)Wv[1], (const T*)Wv[2], (const T*)nullptr, (T)-1, (T)0, kc);
+  HIPCHECK(c, hipGetLastError());
+  return MM_OK;
+}
+
+template <typename T>
+mm_status adj_seed(mm_ctx* c, int i0, void* const* E1, void* const* H1) {
+  AdjWork& w = *c->adjw;
+  Geo g = make_geo(c);
+  const int NY = nodes(c, 1), NZ = nodes(c, 2);
+  hipLaunchKernelGGL((mmk::adj_seed_flux<T>), dim3((NY * NZ + 255) / 256), dim3(256), 0, c->stream, g,
+                     (T*)w.Eb[1], (T*)w.Eb[2], (T*)w.Hb[1], (T*)w.Hb[2], (const T*)E1[1], (const T*)E1[2],
+                     (const T*)H1[1], (const T*)H1[2], i0, c->dt * c->dy * c->dz, NY, NZ);
+  HIPCHECK(c, hipGetLastError());
+  return MM_OK;
+}
+
+template <typename T>
+mm_status adjoint_run(mm_ctx* c, int i0, double* grad_eps, double* grad_Ms) {
+  mm_status s = adj_alloc(c);
+  if (s) return s;
+  AdjWork& w = *c->adjw;
+  const size_t fb = c->nelem * c->esz, fd = c->nelem * sizeof(double);
+  const size_t ntot = c->h_idx.size();
+  const long N = c->step;
+  const int sub0 = c->substep;
+  const int K = w.K;
+  for (int a = 0; a < 3; ++a) {
+    HIPCHECK(c, hipMemsetAsync(w.Eb[a], 0, fb, c->stream));
+    HIPCHECK(c, hipMemsetAsync(w.Hb[a], 0, fb, c->stream));
+    HIPCHECK(c, hipMemsetAsync(w.epsb[a], 0, fd, c->stream));
+  }
+  if (c->nmag > 0) {
+    for (int a = 0; a < 3; ++a) HIPCHECK(c, hipMemsetAsync(w.Mb[a], 0, std::max<size_t>(ntot, 1) * 8, c->stream));
+    HIPCHECK(c, hipMemsetAsync(w.msf_b, 0, (size_t)c->nmag * 8, c->stream));
+    HIPCHECK(c, hipMemsetAsync(w.aoms_b, 0, (size_t)c->nmag * 8, c->stream));
+  }
+  s = copy_state(c, w.fin, true);
+  if (s) return s;
+  const size_t lsub = (size_t)w.cap * std::max(c->nmag, 1);
+  const long nseg = (N + K - 1) / K;
+  std::vector<int> iters;
+  for (long sg = nseg - 1; sg >= 0; --sg) {
+    const long n0 = sg * K, n1 = std::min<long>(N, n0 + K);
+    const int len = (int)(n1 - n0);
+    s = copy_state(c, c->ckpts[sg], false);
+    if (s) return s;
+    c->step = n0;
+    c->substep = (int)(2 * n0);
+    c->adj_recompute = true;
+    for (int j = 0; j < len; ++j) {
+      if ((s = copy3(c, w.sE[j], c->E, true)) || (s = copy3(c, w.sH[j], c->H, true)) || (s = copyM(c, w.sM[j], true)))
+        return s;
+      c->hlog_cur = w.slog[j];
+      if ((s = substep<T>(c))) return s;
+      if ((s = copy3(c, w.sHh[j], c->H, true)) || (s = copyM(c, w.sMh[j], true))) return s;
+      if ((s = e_step<T>(c))) return s;
+      c->hlog_cur = w.slog[j] + lsub;
+      if ((s = substep<T>(c))) return s;
+      c->step++;
+    }
+    c->hlog_cur = nullptr;
+    c->adj_recompute = false;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    iters.assign(2 * len, 1);
+    if (c->nmag > 0)
+      HIPCHECK(c, hipMemcpy(iters.data(), c->d_iters + 2 * n0, 2 * len * sizeof(int), hipMemcpyDeviceToHost));
+    int ew = 0;
+    HIPCHECK(c, hipMemcpy(&ew, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (ew & 8) return fail(c, MM_ESTATE, "a sub-step needed more iterations than the adjoint log holds (%d)", w.cap);
+    for (int j = len - 1; j >= 0; --j) {
+      // level n+1: the next stored step, or the live fields after the segment's last step
+      T* E1[3];
+      T* H1[3];
+      T* Hh[3];
+      T* Hn[3];
+      for (int a = 0; a < 3; ++a) {
+        E1[a] = j + 1 < len ? arr3<T>(w.sE[j + 1], c, a) : (T*)c->E[a];
+        H1[a] = j + 1 < len ? arr3<T>(w.sH[j + 1], c, a) : (T*)c->H[a];
+        Hh[a] = arr3<T>(w.sHh[j], c, a);
+        Hn[a] = arr3<T>(w.sH[j], c, a);
+      }
+      if ((s = adj_seed<T>(c, i0, (void* const*)E1, (void* const*)H1))) return s;
+      // Step 3: input (H, M)^{n+1/2}, output H^{n+1}
+      if ((s = adj_substep<T>(c, Hh, w.sMh[j], H1, w.slog[j] + lsub, iters[2 * j + 1]))) return s;
+      // Step 2
+      c->step = n0 + j;
+      if ((s = adj_estep<T>(c, w.sE[j], w.sHh[j]))) return s;
+      // Step 1: input (H, M)^n, output H^{n+1/2}
+      if ((s = adj_substep<T>(c, Hn, w.sM[j], Hh, w.slog[j], iters[2 * j]))) return s;
+    }
+  }
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  // ---- parameter chains (host) ----
+  const size_t ncells = (size_t)c->nx * c->ny * c->nz;
+  std::fill(grad_eps, grad_eps + ncells, 0.0);
+  std::fill(grad_Ms, grad_Ms + ncells, 0.0);
+  auto cidx = [&](int i, int j, int k) {
+    const int n[3] = {c->nx, c->ny, c->nz};
+    int p[3] = {i, j, k};
+    for (int a = 0; a < 3; ++a) {
+      if (p[a] < 0) p[a] += n[a];
+      if (p[a] >= n[a]) p[a] -= n[a];
+    }
+    return (size_t)p[0] + (size_t)c->nx * ((size_t)p[1] + (size_t)c->ny * p[2]);
+  };
+  {
+    std::vector<double> eb(c->nelem);
+    for (int comp = 0; comp < 3; ++comp) {
+      HIPCHECK(c, hipMemcpy(eb.data(), w.epsb[comp], fd, hipMemcpyDeviceToHost));
+      const int t1 = comp == 0 ? 1 : 0, t2 = comp == 2 ? 1 : 2;
+      for (int k = 0; k < c->nz; ++k)
+        for (int j = 0; j < c->ny; ++j)
+          for (int i = 0; i < c->nx; ++i) {
+            if (!entry_interior(c, comp, i, j, k)) continue;
+            const double gv = mmk::kEps0 * 0.25 * eb[pidx(c, i, j, k)];
+            if (gv == 0.0) continue;
+            for (int u = 0; u < 2; ++u)
+              for (int v = 0; v < 2; ++v) {
+                int q[3] = {i, j, k};
+                q[t1] -= 1 - u;
+                q[t2] -= 1 - v;
+                grad_eps[cidx(q[0], q[1], q[2])] += gv;
+              }
+          }
+    }
+  }
+  if (!ntot) {
+    s = copy_state(c, w.fin, false);
+    c->step = N;
+    c->substep = sub0;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return s;
+  }
+  std::vector<double> mb[3], msf(c->nmag), aob(c->nmag), Msf(ntot), aoms(ntot);
+  for (int a = 0; a < 3; ++a) {
+    mb[a].assign(ntot, 0.0);
+    HIPCHECK(c, hipMemcpy(mb[a].data(), w.Mb[a], ntot * 8, hipMemcpyDeviceToHost));
+  }
+  if (c->nmag) {
+    HIPCHECK(c, hipMemcpy(msf.data(), w.msf_b, c->nmag * 8, hipMemcpyDeviceToHost));
+    HIPCHECK(c, hipMemcpy(aob.data(), w.aoms_b, c->nmag * 8, hipMemcpyDeviceToHost));
+  }
+  HIPCHECK(c, hipMemcpy(Msf.data(), c->d_Ms, ntot * 8, hipMemcpyDeviceToHost));
+  HIPCHECK(c, hipMemcpy(aoms.data(), c->d_aoms, ntot * 8, hipMemcpyDeviceToHost));
+  for (size_t t = 0; t < (size_t)c->nmag; ++t) {
+    const FaceCells& fc = c->fcells[t];
+    // d L / d Ms_f: through N(M) and alpha/Ms (d(alpha/Ms)/dMs = -aoms/Ms)
+    double gtot = msf[t] + aob[t] * (-aoms[t] / Msf[t]);
+    // initial M0_f = v Ms_f / |v|, v = mean of Ms * m0 over the face's cells
+    const double nv = std::sqrt((fc.v[0] * fc.v[0] + fc.v[1] * fc.v[1]) + fc.v[2] * fc.v[2]);
+    const double vh[3] = {fc.v[0] / nv, fc.v[1] / nv, fc.v[2] / nv};
+    const double m0b[3] = {mb[0][t], mb[1][t], mb[2][t]};
+    const double pr = (vh[0] * m0b[0] + vh[1] * m0b[1]) + vh[2] * m0b[2];
+    gtot += pr;
+    double vb[3];
+    for (int a = 0; a < 3; ++a) vb[a] = (Msf[t] / nv) * (m0b[a] - vh[a] * pr);
+    if (fc.b < 0) {   // one cell (PEC wall face)
+      grad_Ms[fc.a] += gtot + ((fc.ma[0] * vb[0] + fc.ma[1] * vb[1]) + fc.ma[2] * vb[2]);
+    } else {
+      grad_Ms[fc.a] += 0.5 * gtot + 0.5 * ((fc.ma[0] * vb[0] + fc.ma[1] * vb[1]) + fc.ma[2] * vb[2]);
+      grad_Ms[fc.b] += 0.5 * gtot + 0.5 * ((fc.mb[0] * vb[0] + fc.mb[1] * vb[1]) + fc.mb[2] * vb[2]);
+    }
+  }
+  for (size_t q = 0; q < ncells; ++q)
+    if (!c->cell_mag[q]) grad_Ms[q] = 0.0;
+  s = copy_state(c, w.fin, false);
+  c->step = N;
+  c->substep = sub0;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  return s;
+}

@@ -13,10 +13,13 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/mm.h"
 #include "kernels.h"
+#include "adjoint.h"
 
 using mmk::Geo;
 
@@ -28,6 +31,16 @@ struct ProbeRec {
   mm_probe_desc d;
   mmk::PointProbe pp;  // for kind 0
 };
+
+// The cells behind a magnetic face (for the Ms chain of the adjoint): cell
+// indices (b = -1 on a PEC wall face), their m0 directions, and v, the mean
+// of Ms * m0 before renormalisation to the face Ms.
+struct FaceCells {
+  long long a, b;
+  double ma[3], mb[3], v[3];
+};
+
+struct AdjWork;
 
 }  // namespace
 
@@ -113,7 +126,9 @@ struct mm_ctx {
   bool adj_recompute;         // true while the adjoint recomputes a segment (no probes)
   int ckpt_every;             // 0: adjoint disabled
   std::vector<void*> ckpts;   // one device block per checkpoint
-  size_t ckpt_bytes;
+  AdjWork* adjw;
+  std::vector<FaceCells> fcells;   // per magnetic face (evolving first)
+  std::vector<bool> cell_mag;      // Ms > 0 per cell
 
   // optional kernel timing (mm_profile)
   bool prof;
@@ -288,7 +303,7 @@ mm_status freeze_probes(mm_ctx* c) {
     HIPCHECK(c, hipMemcpy(c->d_points, pts.data(), pts.size() * sizeof(mmk::PointProbe), hipMemcpyHostToDevice));
   }
   if (c->nflux) {
-    c->flux_blocks = 32;
+    c->flux_blocks = 256;
     c->d_planes = (int*)dalloc(c, planes.size() * sizeof(int));
     c->d_slots = (int*)dalloc(c, slots.size() * sizeof(int));
     c->d_partial = (double*)dalloc(c, (size_t)c->nflux * 2 * c->flux_blocks * sizeof(double));
@@ -460,13 +475,7 @@ mm_status substep(mm_ctx* c) {
   return MM_OK;
 }
 
-template <typename T>
-mm_status one_step(mm_ctx* c) {
-  mm_status s = substep<T>(c);  // Step 1
-  if (s) return s;
-  const Geo g = make_geo(c);
-  dim3 grid;
-  const int kc = kchunk_for(c, grid);
+mmk::Src make_src(const mm_ctx* c) {
   mmk::Src src;
   std::memset(&src, 0, sizeof src);
   src.comp = -1;
@@ -479,21 +488,34 @@ mm_status one_step(mm_ctx* c) {
     }
     src.g = waveform(((double)c->step + 0.5) * c->dt, c->f0, c->Tp, c->t0);
   }
-  {
-    Timed tm(c, 0);
-    if (c->sig)
-      hipLaunchKernelGGL((mmk::e_update<T, true>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->E[0], (T*)c->E[1],
-                         (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], (const T*)c->eps,
-                         (const T*)c->sig, (T)c->dt, src, kc);
-    else
-      hipLaunchKernelGGL((mmk::e_update<T, false>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->E[0], (T*)c->E[1],
-                         (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], (const T*)c->eps,
-                         (const T*)c->sig, (T)c->dt, src, kc);
-  }
+  return src;
+}
+
+// Step 2 of step c->step.
+template <typename T>
+mm_status e_step(mm_ctx* c) {
+  const Geo g = make_geo(c);
+  dim3 grid;
+  const int kc = kchunk_for(c, grid);
+  const mmk::Src src = make_src(c);
+  Timed tm(c, 0);
+  if (c->sig)
+    hipLaunchKernelGGL((mmk::e_update<T, true>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->E[0], (T*)c->E[1],
+                       (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], (const T*)c->eps,
+                       (const T*)c->sig, (T)c->dt, src, kc);
+  else
+    hipLaunchKernelGGL((mmk::e_update<T, false>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->E[0], (T*)c->E[1],
+                       (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], (const T*)c->eps,
+                       (const T*)c->sig, (T)c->dt, src, kc);
   HIPCHECK(c, hipGetLastError());
-  s = substep<T>(c);  // Step 3
-  if (s) return s;
-  // probes at level n+1
+  return MM_OK;
+}
+
+// Probe sampling at level c->step + 1.
+template <typename T>
+mm_status record_probes(mm_ctx* c) {
+  if (c->adj_recompute) return MM_OK;
+  const Geo g = make_geo(c);
   Timed tm(c, 5);
   if (c->npoints)
     hipLaunchKernelGGL((mmk::probe_points<T>), dim3((c->npoints + 63) / 64), dim3(64), 0, c->stream, c->d_points,
@@ -505,6 +527,19 @@ mm_status one_step(mm_ctx* c) {
                        c->series_cap, c->d_sums, c->step, c->dt, c->dy * c->dz, NY, NZ);
   }
   HIPCHECK(c, hipGetLastError());
+  return MM_OK;
+}
+
+template <typename T>
+mm_status one_step(mm_ctx* c) {
+  mm_status s = substep<T>(c);  // Step 1
+  if (s) return s;
+  s = e_step<T>(c);             // Step 2
+  if (s) return s;
+  s = substep<T>(c);            // Step 3
+  if (s) return s;
+  s = record_probes<T>(c);
+  if (s) return s;
   c->step++;
   return MM_OK;
 }
@@ -574,6 +609,10 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
   // Ms*m0_dir renormalised to Ms_f (Sec. 3.1).
   std::vector<int> ev_idx[3], wl_idx[3];
   std::vector<double> ev_v[3][7], wl_v[3][7];  // Ms, kap, aoms, M0x, M0y, M0z, unused
+  std::vector<FaceCells> ev_fc[3], wl_fc[3];
+  c->cell_mag.assign(ncells, false);
+  if (mat->Ms)
+    for (size_t q = 0; q < ncells; ++q) c->cell_mag[q] = mat->Ms[q] > 0;
   for (int f = 0; f < 3; ++f) {
     int ext[3];
     field_extent(c, 3 + f, ext);
@@ -636,12 +675,35 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
           const double kap = mmk::kMu0 * gf * c->dt / 4.0;
           const double vals[7] = {Msf, kap, af / Msf, M0[0] * sc, M0[1] * sc, M0[2] * sc, 0.0};
           const int pi = (int)pidx(c, i, j, k);
+          FaceCells fcl;
+          auto lin = [&](const int q[3]) {
+            return (long long)q[0] + (long long)c->nx * ((long long)q[1] + (long long)c->ny * q[2]);
+          };
+          if (wall) {
+            const int* q = (p[f] == 0) ? qb : qa;
+            fcl.a = lin(q);
+            fcl.b = -1;
+            for (int cc = 0; cc < 3; ++cc) {
+              fcl.ma[cc] = mdir(cc, q);
+              fcl.mb[cc] = 0.0;
+            }
+          } else {
+            fcl.a = lin(qa);
+            fcl.b = lin(qb);
+            for (int cc = 0; cc < 3; ++cc) {
+              fcl.ma[cc] = mdir(cc, qa);
+              fcl.mb[cc] = mdir(cc, qb);
+            }
+          }
+          for (int cc = 0; cc < 3; ++cc) fcl.v[cc] = M0[cc];
           if (wall) {
             wl_idx[f].push_back(pi);
             for (int v = 0; v < 7; ++v) wl_v[f][v].push_back(vals[v]);
+            wl_fc[f].push_back(fcl);
           } else {
             ev_idx[f].push_back(pi);
             for (int v = 0; v < 7; ++v) ev_v[f][v].push_back(vals[v]);
+            ev_fc[f].push_back(fcl);
           }
         }
   }
@@ -653,6 +715,9 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
   std::vector<double> hv[7];
   c->h_idx.clear();
   c->h_fam.clear();
+  c->fcells.clear();
+  for (int f = 0; f < 3; ++f) c->fcells.insert(c->fcells.end(), ev_fc[f].begin(), ev_fc[f].end());
+  for (int f = 0; f < 3; ++f) c->fcells.insert(c->fcells.end(), wl_fc[f].begin(), wl_fc[f].end());
   for (int f = 0; f < 3; ++f) {
     c->h_idx.insert(c->h_idx.end(), ev_idx[f].begin(), ev_idx[f].end());
     c->h_fam.insert(c->h_fam.end(), ev_idx[f].size(), f);
@@ -790,6 +855,8 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
   return MM_OK;
 }
 
+#include "adjoint_host.h"
+
 void release(mm_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
@@ -803,6 +870,8 @@ void release(mm_ctx* c) {
     c->h_ring = nullptr;
   }
   while (!c->allocs.empty()) dfree(c, c->allocs.back().first);
+  delete c->adjw;
+  c->adjw = nullptr;
 }
 
 }  // namespace
@@ -894,6 +963,10 @@ mm_status mm_step(mm_ctx* c, int64_t n) {
   s = grow_buffers(c, (size_t)(c->step + n));
   if (s) return s;
   for (int64_t q = 0; q < n; ++q) {
+    if (c->ckpt_every > 0 && c->step % c->ckpt_every == 0) {
+      s = save_checkpoint(c, (size_t)(c->step / c->ckpt_every));
+      if (s) return s;
+    }
     s = c->prec == MM_FP32 ? one_step<float>(c) : one_step<double>(c);
     if (s) return s;
   }
@@ -1142,6 +1215,32 @@ mm_status mm_info(const mm_ctx* c, int64_t out[8]) {
   out[6] = (int64_t)c->esz;
   out[7] = (int64_t)c->dev_bytes;
   return MM_OK;
+}
+
+mm_status mm_adjoint_enable(mm_ctx* c, int32_t checkpoint_every) {
+  if (!c) return MM_EINVAL;
+  if (checkpoint_every < 1) return fail(c, MM_EINVAL, "checkpoint_every must be >= 1");
+  if (c->step != 0) return fail(c, MM_ESTATE, "the adjoint must be enabled before the first step");
+  if (c->mu) return fail(c, MM_EINVAL, "the adjoint supports mu_r = 1 only");
+  c->ckpt_every = checkpoint_every;
+  return MM_OK;
+}
+
+mm_status mm_adjoint(mm_ctx* c, int32_t probe_id, double* grad_eps_r, double* grad_Ms) {
+  if (!c || !grad_eps_r || !grad_Ms) return MM_EINVAL;
+  if (c->ckpt_every <= 0) return fail(c, MM_ESTATE, "mm_adjoint_enable was not called before stepping");
+  if (probe_id < 0 || (size_t)probe_id >= c->probes.size() || c->probes[probe_id].d.kind != 1)
+    return fail(c, MM_EINVAL, "the loss probe must be a flux probe");
+  if (c->step == 0) return fail(c, MM_ESTATE, "no steps to differentiate");
+  mm_status s = mm_sync(c);
+  if (s) return s;
+  const int i0 = c->probes[probe_id].d.i;
+  s = c->prec == MM_FP32 ? adjoint_run<float>(c, i0, grad_eps_r, grad_Ms)
+                         : adjoint_run<double>(c, i0, grad_eps_r, grad_Ms);
+  if (s) return s;
+  s = read_sticky(c);
+  if (s) return s;
+  return take_sticky(c);
 }
 
 mm_status mm_profile(mm_ctx* c, int32_t enable) {

@@ -101,6 +101,10 @@ typedef struct {
   void *(*dev_alloc)(size_t bytes, void *ctx);
   void (*dev_free)(void *ptr, void *ctx);
   void *alloc_ctx;
+  int32_t scheme;         /* 0 or 2: the second-order iterative H-M sub-step
+                             (Sec. 3.2.2); 1: the first-order scheme of Sec. 3.2.1
+                             (one explicit Landau-Lifshitz step of M per half step,
+                             then eq:H_update; tol, max_iter and fixed_iter unused) */
 } mm_options;
 
 typedef struct mm_ctx mm_ctx;
@@ -164,9 +168,26 @@ mm_status mm_sync(mm_ctx *c);
  * device bytes held by the context. */
 mm_status mm_info(const mm_ctx *c, int64_t out[8]);
 
+/* Device layout: out[0..7] = bulk tiles (64 x 4 cells x out[5] planes),
+ * tiles near evolving magnetic faces (they take each Faraday half step on
+ * its own, in sub-step order), far tiles (within one mm_step call they take
+ * the two half steps that use the same curl E, Step 3 of one step and Step
+ * 1 of the next, in one fused pass), cells in near tiles, cells in far
+ * tiles, planes per tile, the number of distinct (eps_r, sigma) pairs when
+ * the E update reads byte material ids instead of the two cell maps (at
+ * most 256; 0: dense maps), 0.  The far tiles' lag is invisible at the
+ * interface: probes read the level they sample, and every call ends with
+ * all tiles at level n. */
+mm_status mm_layout(const mm_ctx *c, int64_t out[8]);
+
 /* Adjoint (an addition to the paper's method).  mm_adjoint_enable, called
  * before the first step, makes mm_step save the state (E, H, M) every
- * `checkpoint_every` steps (device memory held by the context).
+ * `checkpoint_every` steps (device memory held by the context).  With
+ * 0 < inner_every < checkpoint_every the adjoint is two-level: each
+ * segment is recomputed once to save the state every inner_every steps,
+ * and per-step storage is held for inner_every steps instead of
+ * checkpoint_every (one more forward recompute, far less memory);
+ * inner_every = 0 is single-level.  Requires the second-order scheme.
  * mm_adjoint then returns, in host arrays of nx*ny*nz doubles (cell maps,
  * x fastest), the gradient of L = sum_{n=1}^{N} dt P^n -- the
  * time-integrated value of flux probe `probe_id` over the N steps taken --
@@ -179,16 +200,17 @@ mm_status mm_info(const mm_ctx *c, int64_t out[8]);
  * and probes as they were.  Requirements: mu_r = 1 everywhere (MM_EINVAL
  * from mm_adjoint_enable otherwise), a flux probe, at most 16 iterations
  * per sub-step (MM_ESTATE otherwise).  Synchronises the stream. */
-mm_status mm_adjoint_enable(mm_ctx *c, int32_t checkpoint_every);
+mm_status mm_adjoint_enable(mm_ctx *c, int32_t checkpoint_every, int32_t inner_every);
 mm_status mm_adjoint(mm_ctx *c, int32_t probe_id, double *grad_eps_r, double *grad_Ms);
 
 /* Kernel timing.  mm_profile(c, 1) makes every later mm_step bracket each
  * kernel launch with a pair of HIP events on the context's stream (class
- * 0 e_update, 1 h_bulk, 2 hm_pre, 3 hm_step, 4 hm_finish, 5 probes,
- * 6 hm_commit); mm_profile(c, 0) stops recording.  mm_profile_read
- * synchronises, writes the summed elapsed milliseconds and the launch counts
- * of each class to ms[0..7] / counts[0..7] (class 7 unused) and discards
- * the records. */
+ * 0 e_update, 1 h_bulk (one half step: every tile, or the near tiles),
+ * 2 hm_pre, 3 hm_step, 4 hm_finish, 5 probes, 6 hm_commit, 7 h_far (the
+ * fused two half steps of the far tiles)); mm_profile(c, 0) stops
+ * recording.  mm_profile_read synchronises, writes the summed elapsed
+ * milliseconds and the launch counts of each class to ms[0..7] /
+ * counts[0..7] and discards the records. */
 mm_status mm_profile(mm_ctx *c, int32_t enable);
 mm_status mm_profile_read(mm_ctx *c, double ms[8], int64_t counts[8]);
 

@@ -21,6 +21,10 @@ Coupled Electrodynamics-Micromagnetics Solver".
     iterated until the domain-wide max of |dM|/Ms drops below tol; faces
     with Ms = 0 take the plain Faraday update with mu.
   * Sec. 3.2.3: periodic and PEC boundaries.
+  * Sec. 3.2.1 Steps 1 and 3 (scheme=1): the first-order scheme, an
+    explicit step of the LLG in Landau-Lifshitz form (eq:LLG_scalar, with
+    gamma_L = gamma / (1 + alpha^2)) then N(M) and eq:H_update /
+    eq:H_update2; read with dt/2 for each half step.
 
 Readings where the paper is silent or ambiguous (each one is listed in the
 design notes): the residual is the max over magnetic faces and components of
@@ -155,7 +159,9 @@ class Simulation:
     time step `dt`, cell-centred material maps (host layout, None -> default),
     uniform bias `H0`, optional soft source (comp, profile, f0, Tp, t0),
     per-axis periodic flags, sub-step tolerance / iteration cap, and
-    `fixed_iter` (> 0: exactly that many iterations per sub-step).
+    `fixed_iter` (> 0: exactly that many iterations per sub-step), and
+    `scheme` (2: the iterative second-order sub-step; 1: the first-order
+    scheme of Sec. 3.2.1, one explicit update per sub-step).
     `dtype` complex128 runs the same arithmetic on complex numbers (all
     decisions use real parts), for complex-step derivatives in the tests.
     """
@@ -163,8 +169,10 @@ class Simulation:
     def __init__(self, n, d, dt, eps_r=None, sigma=None, mu_r=None, Ms=None,
                  alpha=None, gamma=None, m0_dir=None, H0=(0.0, 0.0, 0.0),
                  source=None, periodic=(False, False, False), tol=1e-10,
-                 max_iter=100, fixed_iter=0, raise_on_noconv=False, dtype=np.float64):
+                 max_iter=100, fixed_iter=0, raise_on_noconv=False, dtype=np.float64, scheme=2):
         self.dtype = np.dtype(dtype)
+        assert scheme in (1, 2)
+        self.scheme = int(scheme)
         self.n = tuple(int(v) for v in n)
         self.d = tuple(float(v) for v in d)
         self.dt = float(dt)
@@ -356,11 +364,44 @@ class Simulation:
             out.append(hc + self.H0[c])
         return out
 
+    # ---- Step 1 / Step 3 of the first-order scheme (Sec. 3.2.1) -----------
+    def hm_substep_first_order(self, C):
+        """M^{new} = N(M + (dt/2) [mu0 gamma_L M x H_eff + (alpha mu0 gamma_L / Ms)
+        M x (M x H_eff)]) with H_eff from the current H, then
+        H^{new} = H + M_n - M^{new}_n - (dt / 2 mu0) curl E; faces with Ms = 0
+        take the plain Faraday update with mu."""
+        h = 0.5 * self.dt
+        Hs = [a.copy() for a in self.H]
+        Mn_all, Hn_all = [], []
+        for f in range(3):
+            ev = self.evolve[f]
+            M = self.M[f]
+            He = self.H_eff(Hs, f)
+            gL = self.gamma_f[f] / (1.0 + self.alpha_f[f] ** 2)
+            k1 = MU0 * gL
+            with np.errstate(divide="ignore", invalid="ignore"):
+                k2 = np.where(self.mag[f], self.alpha_f[f] * MU0 * gL / np.where(self.mag[f], self.Ms_f[f], 1.0), 0.0)
+            mxh = cross(M, He)
+            mxmxh = cross(M, mxh)
+            Mt = [M[c] + h * (k1 * mxh[c] + k2 * mxmxh[c]) for c in range(3)]
+            Mn = renormalise(Mt, self.Ms_f[f])
+            Mn = [np.where(ev, Mn[c], M[c]) for c in range(3)]
+            q = Hs[f] + M[f] - (h / MU0) * C[f]
+            H_nonmag = np.where(self.h_interior[f], Hs[f] - (h / self.mu_f[f]) * C[f], Hs[f])
+            Hn_all.append(np.where(ev, q - Mn[f], H_nonmag))
+            Mn_all.append(Mn)
+        self.H = Hn_all
+        self.M = Mn_all
+        self.iters.append(1)
+
     # ---- Step 1 / Step 3: the iterative H-M sub-step (Sec. 3.2.2) ----------
     def hm_substep(self, C, trace=None):
         """One H-M sub-step from the current (H, M) with face curl C.  With a
         dict `trace`, records its inputs and the iterate H^{(r-1)} read by each
         iteration r (what the reverse sweep replays)."""
+        if self.scheme == 1:
+            assert trace is None, "the reverse sweep covers the second-order scheme only"
+            return self.hm_substep_first_order(C)
         h = 0.5 * self.dt
         Hs = [a.copy() for a in self.H]
         Ms0 = [[v.copy() for v in self.M[f]] for f in range(3)]

@@ -68,14 +68,15 @@ class Sim:
     Arguments follow mm_init: grid cells `n`, spacings `d`, time step `dt`,
     cell maps in host layout (x fastest: numpy shape (nz, ny, nx)), bias
     `H0`, optional source (comp, profile, f0, Tp, t0), periodic flags,
-    precision 'fp64' or 'fp32', tol, max_iter, fixed_iter.  `stream` is a
-    raw hipStream_t (int) or None for torch's current stream.
+    precision 'fp64' or 'fp32', tol, max_iter, fixed_iter, and `scheme` 2
+    (second-order, iterative) or 1 (first-order).  `stream` is a raw
+    hipStream_t (int) or None for torch's current stream.
     """
 
     def __init__(self, n, d, dt, eps_r=None, sigma=None, mu_r=None, Ms=None, alpha=None,
                  gamma=None, m0_dir=None, H0=(0.0, 0.0, 0.0), source=None,
                  periodic=(False, False, False), precision="fp64", tol=1e-10, max_iter=100,
-                 fixed_iter=0, stream=None, torch_alloc=True):
+                 fixed_iter=0, stream=None, torch_alloc=True, scheme=2):
         self._lib = N.load()
         self._ctx = C.c_void_p()
         g = N.mm_grid(int(n[0]), int(n[1]), int(n[2]),
@@ -102,6 +103,7 @@ class Sim:
         opt.tol = float(tol)
         opt.max_iter = int(max_iter)
         opt.fixed_iter = int(fixed_iter)
+        opt.scheme = int(scheme)
         opt.hip_stream = self.stream or None
         self._alloc = None
         if torch_alloc:
@@ -193,9 +195,19 @@ class Sim:
         keys = ["n_mag", "n_wall_mag", "n_src", "px", "py", "pz", "elem_bytes", "device_bytes"]
         return dict(zip(keys, list(out)))
 
-    def enable_adjoint(self, checkpoint_every=100):
-        """Save checkpoints while stepping so that adjoint() can run (before the first step)."""
-        self._check(self._lib.mm_adjoint_enable(self._ctx, int(checkpoint_every)))
+    def tiles(self):
+        """Bulk tiling, its near/far split and the material-id mode (see mm_layout)."""
+        out = (C.c_int64 * 8)()
+        self._check(self._lib.mm_layout(self._ctx, out))
+        keys = ["tiles", "near_tiles", "far_tiles", "near_cells", "far_cells", "planes_per_tile",
+                "materials"]
+        return dict(zip(keys, list(out)[:7]))
+
+    def enable_adjoint(self, checkpoint_every=100, inner_every=0):
+        """Save checkpoints while stepping so that adjoint() can run (before the
+        first step); inner_every > 0 makes the adjoint two-level (see
+        mm_adjoint_enable)."""
+        self._check(self._lib.mm_adjoint_enable(self._ctx, int(checkpoint_every), int(inner_every)))
 
     def adjoint(self, probe_id):
         """Gradients (d L/d eps_r, d L/d Ms) as host-layout cell maps, where L is
@@ -206,7 +218,7 @@ class Sim:
         self._check(self._lib.mm_adjoint(self._ctx, int(probe_id), _dp(ge), _dp(gm)))
         return ge, gm
 
-    KERNEL_CLASSES = ["e_update", "h_bulk", "hm_pre", "hm_step", "hm_finish", "probes", "hm_commit"]
+    KERNEL_CLASSES = ["e_update", "h_bulk", "hm_pre", "hm_step", "hm_finish", "probes", "hm_commit", "h_far"]
 
     def profile(self, enable=True):
         """Bracket every later kernel launch with HIP events (see mm_profile)."""

@@ -14,7 +14,7 @@ MM_BC_PEC, MM_BC_PERIODIC = 0, 1
 MM_FP64, MM_FP32 = 0, 1
 
 EXPORTED = ["mm_init", "mm_step", "mm_add_probe", "mm_probe", "mm_get_field", "mm_set_field",
-            "mm_stats", "mm_sync", "mm_info", "mm_adjoint_enable", "mm_adjoint", "mm_profile",
+            "mm_stats", "mm_sync", "mm_info", "mm_layout", "mm_adjoint_enable", "mm_adjoint", "mm_profile",
             "mm_profile_read", "mm_last_error", "mm_destroy"]
 
 _dptr = C.POINTER(C.c_double)
@@ -44,7 +44,8 @@ class mm_source(C.Structure):
 class mm_options(C.Structure):
     _fields_ = [("prec", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("fixed_iter", C.c_int32), ("hip_stream", C.c_void_p),
-                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p)]
+                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p),
+                ("scheme", C.c_int32)]
 
 
 class mm_probe_desc(C.Structure):
@@ -83,7 +84,9 @@ def load(path: str = LIB_PATH):
     lib.mm_sync.restype = C.c_int
     lib.mm_info.argtypes = [P, C.POINTER(C.c_int64)]
     lib.mm_info.restype = C.c_int
-    lib.mm_adjoint_enable.argtypes = [P, C.c_int32]
+    lib.mm_layout.argtypes = [P, C.POINTER(C.c_int64)]
+    lib.mm_layout.restype = C.c_int
+    lib.mm_adjoint_enable.argtypes = [P, C.c_int32, C.c_int32]
     lib.mm_adjoint_enable.restype = C.c_int
     lib.mm_adjoint.argtypes = [P, C.c_int32, _dptr, _dptr]
     lib.mm_adjoint.restype = C.c_int

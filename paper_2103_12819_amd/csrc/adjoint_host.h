@@ -7,12 +7,17 @@
 // and recompute the segment, storing per step E^n, H^n, M^n, H^{n+1/2},
 // M^{n+1/2} and the H iterates of both sub-steps; then reverse the steps
 // (flux seed at n+1, Step 3, Step 2, Step 1) with the kernels of adjoint.h.
+// Two-level (inner spacing K2 < K): the segment is first recomputed once,
+// saving the state every K2 steps, and then reversed K2 steps at a time,
+// so only K2 steps of per-step storage are held.
 // Finally map the edge-eps and face-Ms cotangents to the cell maps on the
 // host and put the final state back.
 
 struct AdjWork {
-  int K = 0;
+  int K = 0;                   // outer checkpoint spacing (steps)
+  int K2 = 0;                  // inner spacing: steps stored per reversed span (K2 <= K)
   int cap = 0;                 // iterate-log slots per sub-step
+  std::vector<void*> ick;      // inner checkpoints of the current outer segment (two-level)
   void* Eb[3] = {};
   void* Hb[3] = {};
   void* Xb[3] = {};
@@ -125,10 +130,11 @@ void touched_faces(const mm_ctx* c, std::vector<int>& idx, std::vector<unsigned 
 }
 
 mm_status adj_alloc(mm_ctx* c) {
-  if (c->adjw && c->adjw->K == c->ckpt_every) return MM_OK;
+  if (c->adjw && c->adjw->K == c->ckpt_every) return MM_OK;   // enable is once, before stepping
   AdjWork* w = new AdjWork();
   c->adjw = w;
   w->K = c->ckpt_every;
+  w->K2 = c->ckpt_inner > 0 ? std::min(c->ckpt_inner, c->ckpt_every) : c->ckpt_every;
   w->cap = std::min(std::max(c->max_iter, c->fixed_iter), 16);
   c->hlog_cap = w->cap;
   const size_t fb = c->nelem * c->esz, fd = c->nelem * sizeof(double);
@@ -183,7 +189,12 @@ mm_status adj_alloc(mm_ctx* c) {
     HIPCHECK(c, hipMemcpy(w->tfam, tf.data(), tf.size(), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(w->tmag, tm.data(), tm.size() * 4, hipMemcpyHostToDevice));
   }
-  for (int j = 0; j < w->K; ++j) {
+  for (int q = 1; q * w->K2 < w->K; ++q) {
+    void* blk = dalloc(c, state_bytes(c));
+    if (!blk) return fail(c, MM_ENOMEM, "inner checkpoint allocation failed");
+    w->ick.push_back(blk);
+  }
+  for (int j = 0; j < w->K2; ++j) {
     void* e = dalloc(c, 3 * fb);
     void* h = dalloc(c, 3 * fb);
     void* hh = dalloc(c, 3 * fb);
@@ -305,8 +316,9 @@ mm_status adj_estep(mm_ctx* c, const void* En, const void* Hh) {
                        arr3<T>(Hh, c, 1), arr3<T>(Hh, c, 2), (const T*)c->eps, (const T*)c->sig, Wv[0], Wv[1],
                        Wv[2], w.epsb[0], w.epsb[1], w.epsb[2], (T)c->dt, src, kc);
   // H_bar += curl E(W): the non-magnetic H kernel with coefficient -1
-  hipLaunchKernelGGL((mmk::h_bulk<T, false>), grid, dim3(64, 4), 0, c->stream, g, Hb[0], Hb[1], Hb[2],
-                     (const T*)Wv[0], (const T*)Wv[1], (const T*)Wv[2], (const T*)nullptr, (T)-1, (T)0, kc);
+  hipLaunchKernelGGL((mmk::h_bulk<T, false, 1>), dim3(c->n_all), dim3(64, 4), 0, c->stream, g, Hb[0], Hb[1],
+                     Hb[2], (const T*)Wv[0], (const T*)Wv[1], (const T*)Wv[2], (const T*)nullptr, (T)-1, (T)0,
+                     tiles(c, c->d_tl_all));
   HIPCHECK(c, hipGetLastError());
   return MM_OK;
 }
@@ -320,6 +332,62 @@ mm_status adj_seed(mm_ctx* c, int i0, void* const* E1, void* const* H1) {
                      (T*)w.Eb[1], (T*)w.Eb[2], (T*)w.Hb[1], (T*)w.Hb[2], (const T*)E1[1], (const T*)E1[2],
                      (const T*)H1[1], (const T*)H1[2], i0, c->dt * c->dy * c->dz, NY, NZ);
   HIPCHECK(c, hipGetLastError());
+  return MM_OK;
+}
+
+// Steps [m0, m0 + len): restore the state saved at m0, recompute the span
+// storing per step E^n, H^n, M^n, H^{n+1/2}, M^{n+1/2} and the iterate logs,
+// then reverse its steps, last first, into the cotangents.
+template <typename T>
+mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
+  AdjWork& w = *c->adjw;
+  const size_t lsub = (size_t)w.cap * std::max(c->nmag, 1);
+  mm_status s = copy_state(c, start, false);
+  if (s) return s;
+  c->step = m0;
+  c->substep = (int)(2 * m0);
+  c->adj_recompute = true;
+  for (int j = 0; j < len; ++j) {
+    if ((s = copy3(c, w.sE[j], c->E, true)) || (s = copy3(c, w.sH[j], c->H, true)) || (s = copyM(c, w.sM[j], true)))
+      return s;
+    c->hlog_cur = w.slog[j];
+    if ((s = substep<T>(c))) return s;
+    if ((s = copy3(c, w.sHh[j], c->H, true)) || (s = copyM(c, w.sMh[j], true))) return s;
+    if ((s = e_step<T>(c))) return s;
+    c->hlog_cur = w.slog[j] + lsub;
+    if ((s = substep<T>(c))) return s;
+    c->step++;
+  }
+  c->hlog_cur = nullptr;
+  c->adj_recompute = false;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  std::vector<int> iters(2 * len, 1);
+  if (c->nmag > 0)
+    HIPCHECK(c, hipMemcpy(iters.data(), c->d_iters + 2 * m0, 2 * len * sizeof(int), hipMemcpyDeviceToHost));
+  int ew = 0;
+  HIPCHECK(c, hipMemcpy(&ew, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  if (ew & 8) return fail(c, MM_ESTATE, "a sub-step needed more iterations than the adjoint log holds (%d)", w.cap);
+  for (int j = len - 1; j >= 0; --j) {
+    // level n+1: the next stored step, or the live fields after the span's last step
+    T* E1[3];
+    T* H1[3];
+    T* Hh[3];
+    T* Hn[3];
+    for (int a = 0; a < 3; ++a) {
+      E1[a] = j + 1 < len ? arr3<T>(w.sE[j + 1], c, a) : (T*)c->E[a];
+      H1[a] = j + 1 < len ? arr3<T>(w.sH[j + 1], c, a) : (T*)c->H[a];
+      Hh[a] = arr3<T>(w.sHh[j], c, a);
+      Hn[a] = arr3<T>(w.sH[j], c, a);
+    }
+    if ((s = adj_seed<T>(c, i0, (void* const*)E1, (void* const*)H1))) return s;
+    // Step 3: input (H, M)^{n+1/2}, output H^{n+1}
+    if ((s = adj_substep<T>(c, Hh, w.sMh[j], H1, w.slog[j] + lsub, iters[2 * j + 1]))) return s;
+    // Step 2
+    c->step = m0 + j;
+    if ((s = adj_estep<T>(c, w.sE[j], w.sHh[j]))) return s;
+    // Step 1: input (H, M)^n, output H^{n+1/2}
+    if ((s = adj_substep<T>(c, Hn, w.sM[j], Hh, w.slog[j], iters[2 * j]))) return s;
+  }
   return MM_OK;
 }
 
@@ -345,57 +413,31 @@ mm_status adjoint_run(mm_ctx* c, int i0, double* grad_eps, double* grad_Ms) {
   }
   s = copy_state(c, w.fin, true);
   if (s) return s;
-  const size_t lsub = (size_t)w.cap * std::max(c->nmag, 1);
   const long nseg = (N + K - 1) / K;
-  std::vector<int> iters;
+  const int K2 = w.K2;
   for (long sg = nseg - 1; sg >= 0; --sg) {
     const long n0 = sg * K, n1 = std::min<long>(N, n0 + K);
-    const int len = (int)(n1 - n0);
-    s = copy_state(c, c->ckpts[sg], false);
-    if (s) return s;
-    c->step = n0;
-    c->substep = (int)(2 * n0);
-    c->adj_recompute = true;
-    for (int j = 0; j < len; ++j) {
-      if ((s = copy3(c, w.sE[j], c->E, true)) || (s = copy3(c, w.sH[j], c->H, true)) || (s = copyM(c, w.sM[j], true)))
-        return s;
-      c->hlog_cur = w.slog[j];
-      if ((s = substep<T>(c))) return s;
-      if ((s = copy3(c, w.sHh[j], c->H, true)) || (s = copyM(c, w.sMh[j], true))) return s;
-      if ((s = e_step<T>(c))) return s;
-      c->hlog_cur = w.slog[j] + lsub;
-      if ((s = substep<T>(c))) return s;
-      c->step++;
-    }
-    c->hlog_cur = nullptr;
-    c->adj_recompute = false;
-    HIPCHECK(c, hipStreamSynchronize(c->stream));
-    iters.assign(2 * len, 1);
-    if (c->nmag > 0)
-      HIPCHECK(c, hipMemcpy(iters.data(), c->d_iters + 2 * n0, 2 * len * sizeof(int), hipMemcpyDeviceToHost));
-    int ew = 0;
-    HIPCHECK(c, hipMemcpy(&ew, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
-    if (ew & 8) return fail(c, MM_ESTATE, "a sub-step needed more iterations than the adjoint log holds (%d)", w.cap);
-    for (int j = len - 1; j >= 0; --j) {
-      // level n+1: the next stored step, or the live fields after the segment's last step
-      T* E1[3];
-      T* H1[3];
-      T* Hh[3];
-      T* Hn[3];
-      for (int a = 0; a < 3; ++a) {
-        E1[a] = j + 1 < len ? arr3<T>(w.sE[j + 1], c, a) : (T*)c->E[a];
-        H1[a] = j + 1 < len ? arr3<T>(w.sH[j + 1], c, a) : (T*)c->H[a];
-        Hh[a] = arr3<T>(w.sHh[j], c, a);
-        Hn[a] = arr3<T>(w.sH[j], c, a);
+    const long nsp = (n1 - n0 + K2 - 1) / K2;   // spans of at most K2 steps
+    // two-level: recompute the segment once, saving the state at the start
+    // of every span after the first (n0 + K2, n0 + 2 K2, ...)
+    if (nsp > 1) {
+      s = copy_state(c, c->ckpts[sg], false);
+      if (s) return s;
+      c->step = n0;
+      c->substep = (int)(2 * n0);
+      c->adj_recompute = true;
+      c->hlog_cur = nullptr;
+      const long last = n0 + (nsp - 1) * K2;
+      while (c->step < last) {
+        if ((s = substep<T>(c)) || (s = e_step<T>(c)) || (s = substep<T>(c))) return s;
+        c->step++;
+        if ((c->step - n0) % K2 == 0 && (s = copy_state(c, w.ick[(c->step - n0) / K2 - 1], true))) return s;
       }
-      if ((s = adj_seed<T>(c, i0, (void* const*)E1, (void* const*)H1))) return s;
-      // Step 3: input (H, M)^{n+1/2}, output H^{n+1}
-      if ((s = adj_substep<T>(c, Hh, w.sMh[j], H1, w.slog[j] + lsub, iters[2 * j + 1]))) return s;
-      // Step 2
-      c->step = n0 + j;
-      if ((s = adj_estep<T>(c, w.sE[j], w.sHh[j]))) return s;
-      // Step 1: input (H, M)^n, output H^{n+1/2}
-      if ((s = adj_substep<T>(c, Hn, w.sM[j], Hh, w.slog[j], iters[2 * j]))) return s;
+      c->adj_recompute = false;
+    }
+    for (long q = nsp - 1; q >= 0; --q) {
+      const long m0 = n0 + q * K2, m1 = std::min<long>(n1, m0 + K2);
+      if ((s = reverse_span<T>(c, i0, m0, (int)(m1 - m0), q == 0 ? c->ckpts[sg] : w.ick[q - 1]))) return s;
     }
   }
   HIPCHECK(c, hipStreamSynchronize(c->stream));

@@ -70,11 +70,37 @@ __device__ __forceinline__ int up(int i, int n, bool per) { return (per && i == 
 
 template <typename T> __device__ __forceinline__ double D(T v) { return (double)v; }
 
+// A bulk launch runs over tiles of 64 x 4 columns x kc planes taken from a
+// list, so the host chooses which tiles run and which XCD (block id mod 8)
+// each lands on.  Tile id = bx + gx (by + gy bz).  With split > 1 each tile
+// is cut along z into `split` runs of ceil(kc / split) planes, one block
+// each (blocks b = split * q + s: tile list[q], run s), for launches over
+// too few tiles to fill the chip.
+struct Tiles {
+  const int* list;
+  int gx, gy, kc, split;
+};
+
+// Origin (i0, j0) and plane range [k0, k1) of this block's run (empty
+// when the tile is shorter than the run's start).
+__device__ __forceinline__ void tile_span(const Tiles& t, int nz, int& i0, int& j0, int& k0, int& k1) {
+  const int q = blockIdx.x / t.split, s = blockIdx.x - q * t.split;
+  const int id = t.list[q];
+  const int bx = id % t.gx, r = id / t.gx;
+  const int ks = (t.kc + t.split - 1) / t.split;
+  const int kt = (r / t.gy) * t.kc;
+  i0 = bx * 64;
+  j0 = (r % t.gy) * 4;
+  k0 = kt + s * ks;
+  k1 = min(min(k0 + ks, kt + t.kc), nz);
+}
+
 // ---------------------------------------------------------------------------
 // Step 2: E^{n+1} = ca E^n + cb curl H^{n+1/2} on interior edges, with eps and
 // sigma on an edge the mean of its 4 cells and ca, cb from the time-centred
 // Ampere law (Sec. 3.2.1, Step 2), with the soft current J^{n+1/2} fused in.
-// Block 64 x 4 threads over (i, j); each thread marches k over [k0, k1).
+// Block 64 x 4 threads over (i, j) of one tile; each thread marches k over
+// the tile's planes.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double src_term(const Src& s, int comp, int i, int j, int k) {
   if (!s.prof || comp != s.comp) return 0.0;
@@ -83,18 +109,31 @@ __device__ __forceinline__ double src_term(const Src& s, int comp, int i, int j,
   return s.prof[(i - s.lo[0]) + bx * ((j - s.lo[1]) + by * (k - s.lo[2]))] * s.g;
 }
 
-template <typename T, bool SIG>
+// MAT: the cell maps come as a byte material id per cell and a table of
+// (eps_r, sigma) per id (exactly the values of the dense maps), staged in
+// LDS: 1 byte per cell instead of two map values.
+template <typename T, bool SIG, bool MAT>
 __global__ __launch_bounds__(256) void e_update(Geo g, T* __restrict__ Ex, T* __restrict__ Ey,
                                                T* __restrict__ Ez, const T* __restrict__ Hx,
                                                const T* __restrict__ Hy, const T* __restrict__ Hz,
-                                               const T* __restrict__ eps, const T* __restrict__ sig,
-                                               T dt, Src src, int kchunk) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * 4 + threadIdx.y;
-  if (i >= g.nx || j >= g.ny) return;
+                                               const T* __restrict__ eps_map, const T* __restrict__ sig_map,
+                                               const unsigned char* __restrict__ mat,
+                                               const T* __restrict__ mtab, T dt, Src src, Tiles tl) {
+  __shared__ T teps[MAT ? 256 : 1], tsig[MAT ? 256 : 1];
+  if (MAT) {
+    const int q = threadIdx.x + 64 * threadIdx.y;
+    teps[q] = mtab[q];
+    tsig[q] = mtab[256 + q];
+    __syncthreads();
+  }
+  auto eps = [&](int a) -> T { return MAT ? teps[mat[a]] : eps_map[a]; };
+  auto sig = [&](int a) -> T { return MAT ? tsig[mat[a]] : sig_map[a]; };
+  int i, j, k0, k1;
+  tile_span(tl, g.nz, i, j, k0, k1);
+  i += threadIdx.x;
+  j += threadIdx.y;
+  if (i >= g.nx || j >= g.ny || k0 >= k1) return;
   const bool pxp = g.per & 1, pyp = g.per & 2, pzp = g.per & 4;
-  const int k0 = blockIdx.z * kchunk;
-  const int k1 = min(k0 + kchunk, g.nz);
   const bool iin = pxp || i >= 1;     // x node interior (Ey, Ez)
   const bool jin = pyp || j >= 1;     // y node interior (Ex, Ez)
   const int im = iin ? dn(i, g.nx, pxp) : i;   // clamped when unused: addresses stay valid
@@ -110,13 +149,13 @@ __global__ __launch_bounds__(256) void e_update(Geo g, T* __restrict__ Ex, T* __
     const int km = dn(k0, g.nz, pzp);
     hx_km = Hx[at(g, i, j, km)];
     hy_km = Hy[at(g, i, j, km)];
-    e_km = eps[at(g, i, j, km)];
-    e_jm_km = eps[at(g, i, jm, km)];
-    e_im_km = eps[at(g, im, j, km)];
+    e_km = eps(at(g, i, j, km));
+    e_jm_km = eps(at(g, i, jm, km));
+    e_im_km = eps(at(g, im, j, km));
     if (SIG) {
-      s_km = sig[at(g, i, j, km)];
-      s_jm_km = sig[at(g, i, jm, km)];
-      s_im_km = sig[at(g, im, j, km)];
+      s_km = sig(at(g, i, j, km));
+      s_jm_km = sig(at(g, i, jm, km));
+      s_im_km = sig(at(g, im, j, km));
     }
   }
   for (int k = k0; k < k1; ++k) {
@@ -127,13 +166,13 @@ __global__ __launch_bounds__(256) void e_update(Geo g, T* __restrict__ Ex, T* __
     const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
     const T hz_jm = Hz[cjm], hx_jm = Hx[cjm];
     const T hz_im = Hz[cim], hy_im = Hy[cim];
-    const T e_c = eps[c], e_jm = eps[cjm], e_im = eps[cim], e_imjm = eps[at(g, im, jm, k)];
+    const T e_c = eps(c), e_jm = eps(cjm), e_im = eps(cim), e_imjm = eps(at(g, im, jm, k));
     T s_c = 0, s_jm = 0, s_im = 0, s_imjm = 0;
     if (SIG) {
-      s_c = sig[c];
-      s_jm = sig[cjm];
-      s_im = sig[cim];
-      s_imjm = sig[at(g, im, jm, k)];
+      s_c = sig(c);
+      s_jm = sig(cjm);
+      s_im = sig(cim);
+      s_imjm = sig(at(g, im, jm, k));
     }
     if (jin && kin) {  // Ex at (i+1/2, j, k)
       T curl = dq(hz - hz_jm, sdy, idy) - dq(hy - hy_km, sdz, idz);
@@ -185,18 +224,24 @@ __global__ __launch_bounds__(256) void e_update(Geo g, T* __restrict__ Ex, T* __
 // H half step with the non-magnetic Faraday law (eq:Faraday3 with the local
 // mu, Sec. 3.2.2): H <- H - (dt/2 mu_f) curl E on every interior face.
 // Magnetic faces are overwritten afterwards by the iteration.
+//
+// NP = 2 applies two half steps with the same curl E in registers: Step 3
+// of step n and Step 1 of step n+1 both use curl E^{n+1}, so on tiles that
+// hold no magnetic face and no face an H_eff of a magnetic face reads, the
+// two passes fuse into one.  Each half step is the same rounded
+// subtraction, so the result equals two NP = 1 launches bit for bit.
 // ---------------------------------------------------------------------------
-template <typename T, bool MU>
+template <typename T, bool MU, int NP>
 __global__ __launch_bounds__(256) void h_bulk(Geo g, T* __restrict__ Hx, T* __restrict__ Hy,
                                              T* __restrict__ Hz, const T* __restrict__ Ex,
                                              const T* __restrict__ Ey, const T* __restrict__ Ez,
-                                             const T* __restrict__ mu, T coef0, T h, int kchunk) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * 4 + threadIdx.y;
-  if (i >= g.nx || j >= g.ny) return;
+                                             const T* __restrict__ mu, T coef0, T h, Tiles tl) {
+  int i, j, k0, k1;
+  tile_span(tl, g.nz, i, j, k0, k1);
+  i += threadIdx.x;
+  j += threadIdx.y;
+  if (i >= g.nx || j >= g.ny || k0 >= k1) return;
   const bool pxp = g.per & 1, pyp = g.per & 2, pzp = g.per & 4;
-  const int k0 = blockIdx.z * kchunk;
-  const int k1 = min(k0 + kchunk, g.nz);
   const bool iin = pxp || i >= 1;
   const bool jin = pyp || j >= 1;
   const int ip = up(i, g.nx, pxp), jp = up(j, g.ny, pyp);
@@ -225,17 +270,23 @@ __global__ __launch_bounds__(256) void h_bulk(Geo g, T* __restrict__ Hx, T* __re
     if (iin) {
       const T curl = dq(ez_jp - ez, sdy, idy) - dq(ey_kp - ey_k, sdz, idz);
       const T cf = MU ? h / (mu0 * (half * (mu[at(g, im, j, k)] + mu_c))) : coef0;
-      Hx[c] = Hx[c] - cf * curl;
+      T v = Hx[c];
+      for (int p = 0; p < NP; ++p) v = v - cf * curl;
+      Hx[c] = v;
     }
     if (jin) {
       const T curl = dq(ex_kp - ex_k, sdz, idz) - dq(ez_ip - ez, sdx, idx);
       const T cf = MU ? h / (mu0 * (half * (mu[at(g, i, jm, k)] + mu_c))) : coef0;
-      Hy[c] = Hy[c] - cf * curl;
+      T v = Hy[c];
+      for (int p = 0; p < NP; ++p) v = v - cf * curl;
+      Hy[c] = v;
     }
     if (pzp || k >= 1) {
       const T curl = dq(ey_ip - ey_k, sdx, idx) - dq(ex_jp - ex_k, sdy, idy);
       const T cf = MU ? h / (mu0 * (half * (mu_km + mu_c))) : coef0;
-      Hz[c] = Hz[c] - cf * curl;
+      T v = Hz[c];
+      for (int p = 0; p < NP; ++p) v = v - cf * curl;
+      Hz[c] = v;
     }
     ex_k = ex_kp;
     ey_k = ey_kp;
@@ -252,6 +303,23 @@ struct Fields {
   T* H[3];
   T* A[3];   // shadow H on magnetic faces (ping-pong partner of H during the iteration)
 };
+
+// Three component pointers held in registers.  A per-thread component index
+// picks one with selects: indexing a pointer array in memory by a value that
+// varies across the wavefront would turn every access into a dependent
+// load of the pointer first.
+template <typename T>
+struct Tri {
+  T* p0;
+  T* p1;
+  T* p2;
+  __device__ __forceinline__ T* operator()(int f) const { return f == 0 ? p0 : (f == 1 ? p1 : p2); }
+};
+
+template <typename T>
+__device__ __forceinline__ Tri<T> tri(T* const (&a)[3]) {
+  return Tri<T>{a[0], a[1], a[2]};
+}
 
 struct Mag {
   const int* idx;            // padded index of the face
@@ -321,27 +389,72 @@ struct HRead {
 // along the face normal first and then along the component's own axis.
 // Neighbour q numbering: first transverse component q = 0..3, second 4..7,
 // in the order (f-1, c), (f, c), (f-1, c+1), (f, c+1).
+//
+// Split into the eight gathers (h_eff_load) and the sums (h_eff_sum) so a
+// kernel can issue every load of a face before the first use.
 template <typename T>
-__device__ __forceinline__ void h_eff(const Geo& g, const HRead<T>& R, double own, int f, int i, int j,
-                                      int k, double H0x, double H0y, double H0z, double he[3]) {
+__device__ __forceinline__ void h_eff_load(const Geo& g, const HRead<T>& R, int f, int i, int j, int k,
+                                           double v[8]) {
   const bool pxp = g.per & 1, pyp = g.per & 2, pzp = g.per & 4;
   const int c = at(g, i, j, k);
   if (f == 0) {
     const int im = dn(i, g.nx, pxp), jp = up(j, g.ny, pyp), kp = up(k, g.nz, pzp);
-    he[0] = own + H0x;
-    he[1] = 0.25 * ((R.v(1, at(g, im, j, k), 0) + R.v(1, c, 1)) + (R.v(1, at(g, im, jp, k), 2) + R.v(1, at(g, i, jp, k), 3))) + H0y;
-    he[2] = 0.25 * ((R.v(2, at(g, im, j, k), 4) + R.v(2, c, 5)) + (R.v(2, at(g, im, j, kp), 6) + R.v(2, at(g, i, j, kp), 7))) + H0z;
+    v[0] = R.v(1, at(g, im, j, k), 0);
+    v[1] = R.v(1, c, 1);
+    v[2] = R.v(1, at(g, im, jp, k), 2);
+    v[3] = R.v(1, at(g, i, jp, k), 3);
+    v[4] = R.v(2, at(g, im, j, k), 4);
+    v[5] = R.v(2, c, 5);
+    v[6] = R.v(2, at(g, im, j, kp), 6);
+    v[7] = R.v(2, at(g, i, j, kp), 7);
   } else if (f == 1) {
     const int jm = dn(j, g.ny, pyp), ip = up(i, g.nx, pxp), kp = up(k, g.nz, pzp);
-    he[0] = 0.25 * ((R.v(0, at(g, i, jm, k), 0) + R.v(0, c, 1)) + (R.v(0, at(g, ip, jm, k), 2) + R.v(0, at(g, ip, j, k), 3))) + H0x;
-    he[1] = own + H0y;
-    he[2] = 0.25 * ((R.v(2, at(g, i, jm, k), 4) + R.v(2, c, 5)) + (R.v(2, at(g, i, jm, kp), 6) + R.v(2, at(g, i, j, kp), 7))) + H0z;
+    v[0] = R.v(0, at(g, i, jm, k), 0);
+    v[1] = R.v(0, c, 1);
+    v[2] = R.v(0, at(g, ip, jm, k), 2);
+    v[3] = R.v(0, at(g, ip, j, k), 3);
+    v[4] = R.v(2, at(g, i, jm, k), 4);
+    v[5] = R.v(2, c, 5);
+    v[6] = R.v(2, at(g, i, jm, kp), 6);
+    v[7] = R.v(2, at(g, i, j, kp), 7);
   } else {
     const int km = dn(k, g.nz, pzp), ip = up(i, g.nx, pxp), jp = up(j, g.ny, pyp);
-    he[0] = 0.25 * ((R.v(0, at(g, i, j, km), 0) + R.v(0, c, 1)) + (R.v(0, at(g, ip, j, km), 2) + R.v(0, at(g, ip, j, k), 3))) + H0x;
-    he[1] = 0.25 * ((R.v(1, at(g, i, j, km), 4) + R.v(1, c, 5)) + (R.v(1, at(g, i, jp, km), 6) + R.v(1, at(g, i, jp, k), 7))) + H0y;
+    v[0] = R.v(0, at(g, i, j, km), 0);
+    v[1] = R.v(0, c, 1);
+    v[2] = R.v(0, at(g, ip, j, km), 2);
+    v[3] = R.v(0, at(g, ip, j, k), 3);
+    v[4] = R.v(1, at(g, i, j, km), 4);
+    v[5] = R.v(1, c, 5);
+    v[6] = R.v(1, at(g, i, jp, km), 6);
+    v[7] = R.v(1, at(g, i, jp, k), 7);
+  }
+}
+
+__device__ __forceinline__ void h_eff_sum(const double v[8], double own, int f, double H0x, double H0y,
+                                          double H0z, double he[3]) {
+  const double t1 = 0.25 * ((v[0] + v[1]) + (v[2] + v[3]));
+  const double t2 = 0.25 * ((v[4] + v[5]) + (v[6] + v[7]));
+  if (f == 0) {
+    he[0] = own + H0x;
+    he[1] = t1 + H0y;
+    he[2] = t2 + H0z;
+  } else if (f == 1) {
+    he[0] = t1 + H0x;
+    he[1] = own + H0y;
+    he[2] = t2 + H0z;
+  } else {
+    he[0] = t1 + H0x;
+    he[1] = t2 + H0y;
     he[2] = own + H0z;
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void h_eff(const Geo& g, const HRead<T>& R, double own, int f, int i, int j,
+                                      int k, double H0x, double H0y, double H0z, double he[3]) {
+  double v[8];
+  h_eff_load(g, R, f, i, j, k, v);
+  h_eff_sum(v, own, f, H0x, H0y, H0z, he);
 }
 
 // One closed-form trapezoidal LLG solve (eq:llg_tra4) followed by N(M):
@@ -373,6 +486,7 @@ __device__ __forceinline__ unsigned long long rbits(double v) {
   return (unsigned long long)__double_as_longlong(fabs(v));
 }
 
+// Max over the block, returned in every thread.
 __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v) {
   __shared__ unsigned long long wmax[16];
   for (int off = 32; off > 0; off >>= 1) {
@@ -382,12 +496,11 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) wmax[w] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int q = 1; q < nw; ++q) v = wmax[q] > v ? wmax[q] : v;
-  }
+  const int nw = (blockDim.x + 63) >> 6;
+  v = wmax[0];
+  for (int q = 1; q < nw; ++q) v = wmax[q] > v ? wmax[q] : v;
   __syncthreads();
-  return v;   // valid in thread 0
+  return v;
 }
 
 __device__ __forceinline__ int face_family(const Mag& m, int t) {
@@ -398,22 +511,49 @@ __device__ __forceinline__ unsigned long long load_u64(const unsigned long long*
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Per-sub-step control block (one per sub-step parity):
-//   ctl[0]      the final iteration count once the stopping rule has fired (0 before)
-//   ctl[r]      max over faces of the residual bits of iteration r (r >= 1)
+// Per-sub-step control (one per sub-step parity).  The residual of
+// iteration r is the max of P per-block partials part[r * P + b], each
+// written with a plain store by block b of the launch that ran iteration r
+// (every slot is written every time, so nothing needs clearing); whoever
+// needs the residual reduces the P partials itself.  One device-scope atomic
+// per block on a single address would serialise across the XCDs (~11 ns
+// each, 140 us for a 12k-block launch).
+//   cur[0]   the final iteration count once the stopping rule has fired (0 before)
 struct Ctl {
   unsigned long long* cur;
-  unsigned long long* next;   // the other sub-step's block, cleared by hm_finish
-  int nres;
+  unsigned long long* next;   // the other sub-step's cur, cleared by hm_commit
+  unsigned long long* part;   // partial maxima of this sub-step, P per iteration
+  int P;
   double tol;
   int max_iter, fixed_iter;
 };
 
-// Stopping rule of Sec. 3.2.2 after iteration r_done has finished:
-// stop on a non-finite residual, on residual < tol, at max_iter, or (fixed
-// mode) after fixed_iter iterations.
-__device__ __forceinline__ bool stop_after(const Ctl& C, int r_done, bool& bad) {
-  const double rv = __longlong_as_double((long long)load_u64(&C.cur[r_done]));
+// Block-wide: the residual bits of iteration r (all threads get the value).
+__device__ __forceinline__ unsigned long long residual_bits(const Ctl& C, int r) {
+  const unsigned long long* p = C.part + (size_t)r * C.P;
+  unsigned long long v = 0;
+  for (int q = threadIdx.x; q < C.P; q += blockDim.x) {
+    const unsigned long long w = load_u64(&p[q]);
+    v = w > v ? w : v;
+  }
+  return block_max_u64(v);
+}
+
+// Block-wide: publish this block's residual bits of iteration r.  A grid
+// smaller than P also fills the slots no block of it owns.
+__device__ __forceinline__ void publish_residual(const Ctl& C, int r, unsigned long long lb) {
+  lb = block_max_u64(lb);
+  unsigned long long* p = C.part + (size_t)r * C.P;
+  if (threadIdx.x == 0)
+    for (int q = blockIdx.x; q < C.P; q += gridDim.x)
+      __hip_atomic_store(&p[q], q == (int)blockIdx.x ? lb : 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Stopping rule of Sec. 3.2.2 after iteration r_done, given its residual
+// bits: stop on a non-finite residual, on residual < tol, at max_iter, or
+// (fixed mode) after fixed_iter iterations.
+__device__ __forceinline__ bool stop_rule(const Ctl& C, int r_done, unsigned long long bits, bool& bad) {
+  const double rv = __longlong_as_double((long long)bits);
   bad = !(rv <= 1.0e308);
   if (bad) return true;
   if (C.fixed_iter > 0) return r_done >= C.fixed_iter;
@@ -425,31 +565,41 @@ __device__ __forceinline__ bool stop_after(const Ctl& C, int r_done, bool& bad) 
 // the residual bits.
 template <typename T>
 __device__ __forceinline__ unsigned long long iterate_faces(const Geo& g, const Mag& m, const Fields<T>& F,
-                                                            T* const* prev, T* const* out, int t0, int stride,
+                                                            Tri<T> prev, Tri<T> out, int t0, int stride,
                                                             double H0x, double H0y, double H0z, int r,
                                                             int* err) {
   unsigned long long lb = 0;
   for (int t = t0; t < m.n; t += stride) {
+    // batch 1: everything indexed by the face number
     const int f = face_family(m, t);
     const int c = m.idx[t];
-    int i, j, k;
-    face_ijk(g, c, i, j, k);
-    HRead<T> Rd;
-    for (int a = 0; a < 3; ++a) {
-      Rd.base[a] = F.H[a];
-      Rd.alt[a] = prev[a];
-    }
-    Rd.mask = m.nbm[t];
-    double he[3];
-    h_eff(g, Rd, D(prev[f][c]), f, i, j, k, H0x, H0y, H0z, he);
-    const double Ms = m.Ms[t];
+    const unsigned mask = m.nbm[t];
+    const double Ms = m.Ms[t], kap = m.kap[t], qf = m.q[t];
     const double d[3] = {m.d[0][t], m.d[1][t], m.d[2][t]};
     const double b[3] = {m.b[0][t], m.b[1][t], m.b[2][t]};
     const double mo[3] = {m.M[0][t], m.M[1][t], m.M[2][t]};
+    __builtin_amdgcn_sched_barrier(0);
+    // batch 2: the face's own H^{(r-1)} and its eight neighbours
+    int i, j, k;
+    face_ijk(g, c, i, j, k);
+    HRead<T> Rd;
+    Rd.base[0] = F.H[0];
+    Rd.base[1] = F.H[1];
+    Rd.base[2] = F.H[2];
+    Rd.alt[0] = prev.p0;
+    Rd.alt[1] = prev.p1;
+    Rd.alt[2] = prev.p2;
+    Rd.mask = mask;
+    double nv[8];
+    const double own = D(prev(f)[c]);
+    h_eff_load(g, Rd, f, i, j, k, nv);
+    __builtin_amdgcn_sched_barrier(0);
+    double he[3];
+    h_eff_sum(nv, own, f, H0x, H0y, H0z, he);
     double mn[3];
-    llg_solve(he, m.kap[t], d, b, Ms, mn);
-    const T hv = (T)(m.q[t] - mn[f]);
-    out[f][c] = hv;
+    llg_solve(he, kap, d, b, Ms, mn);
+    const T hv = (T)(qf - mn[f]);
+    out(f)[c] = hv;
     log_iterate(m, r, t, D(hv), err);
     for (int q3 = 0; q3 < 3; ++q3) {
       m.M[q3][t] = mn[q3];
@@ -463,51 +613,76 @@ __device__ __forceinline__ unsigned long long iterate_faces(const Geo& g, const 
 // Sub-step set-up and iteration r = 1 (which only needs H^s): the
 // iteration-invariant b, d of eq:llg_tra5/6 and q of eq:iterate_H, then
 // M^{(1)} in place and H^{(1)} into the shadow array A.
+//
+// first != 0: the first-order scheme of Sec. 3.2.1 instead.  M^{new} =
+// N(M^s + h [k1 M^s x H_eff^s + k2 M^s x (M^s x H_eff^s)]) with the face
+// constants k1 = mu0 gamma_L, k2 = alpha mu0 gamma_L / Ms held in kap and
+// aoms (eq:LLG_scalar, gamma_L = gamma / (1 + alpha^2)), then H from
+// eq:H_update as in iteration 1; the sub-step ends there.
 template <typename T>
-__global__ __launch_bounds__(256) void hm_pre(Geo g, Fields<T> F, Mag m, double hmu0, double H0x,
-                                             double H0y, double H0z, Ctl C, int* err) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void hm_pre(Geo g, Fields<T> F, Mag m, double h, double hmu0, double H0x,
+                                             double H0y, double H0z, int first, Ctl C, int* err) {
   unsigned long long rb = 0;
-  if (t < m.n) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m.n; t += gridDim.x * blockDim.x) {
+    // batch 1: everything indexed by the face number
     const int f = face_family(m, t);
     const int c = m.idx[t];
+    const double Ms = m.Ms[t], kap = m.kap[t], aoms = m.aoms[t];
+    const double ms[3] = {m.M[0][t], m.M[1][t], m.M[2][t]};
+    __builtin_amdgcn_sched_barrier(0);
+    // batch 2: curl E and H^s around the face
     int i, j, k;
     face_ijk(g, c, i, j, k);
     const double Cf = curl_e_face(g, F, f, i, j, k);
     HRead<T> Rd;
-    for (int a = 0; a < 3; ++a) {
-      Rd.base[a] = F.H[a];
-      Rd.alt[a] = F.H[a];
-    }
+    Rd.base[0] = Rd.alt[0] = F.H[0];
+    Rd.base[1] = Rd.alt[1] = F.H[1];
+    Rd.base[2] = Rd.alt[2] = F.H[2];
     Rd.mask = 0;
-    const double hs = D(F.H[f][c]);
+    const double hs = D(tri(F.H)(f)[c]);
+    double nv[8];
+    h_eff_load(g, Rd, f, i, j, k, nv);
+    __builtin_amdgcn_sched_barrier(0);
     double he[3];
-    h_eff(g, Rd, hs, f, i, j, k, H0x, H0y, H0z, he);
-    const double Ms = m.Ms[t], kap = m.kap[t], aoms = m.aoms[t];
-    const double ms[3] = {m.M[0][t], m.M[1][t], m.M[2][t]};
+    h_eff_sum(nv, hs, f, H0x, H0y, H0z, he);
     // M^s x H_eff^s
     const double mx = ms[1] * he[2] - ms[2] * he[1];
     const double my = ms[2] * he[0] - ms[0] * he[2];
     const double mz = ms[0] * he[1] - ms[1] * he[0];
-    const double b[3] = {ms[0] + kap * mx, ms[1] + kap * my, ms[2] + kap * mz};
-    const double d[3] = {aoms * ms[0], aoms * ms[1], aoms * ms[2]};
     const double q = hs + ms[f] - hmu0 * Cf;
     double mn[3];
-    llg_solve(he, kap, d, b, Ms, mn);
+    if (first) {
+      const double k1 = kap, k2 = aoms;
+      const double xx = ms[1] * mz - ms[2] * my;
+      const double xy = ms[2] * mx - ms[0] * mz;
+      const double xz = ms[0] * my - ms[1] * mx;
+      const double mt[3] = {ms[0] + h * (k1 * mx + k2 * xx), ms[1] + h * (k1 * my + k2 * xy),
+                            ms[2] + h * (k1 * mz + k2 * xz)};
+      const double nrm = sqrt((mt[0] * mt[0] + mt[1] * mt[1]) + mt[2] * mt[2]);
+      const double s = Ms / nrm;
+      mn[0] = mt[0] * s;
+      mn[1] = mt[1] * s;
+      mn[2] = mt[2] * s;
+    } else {
+      const double b[3] = {ms[0] + kap * mx, ms[1] + kap * my, ms[2] + kap * mz};
+      const double d[3] = {aoms * ms[0], aoms * ms[1], aoms * ms[2]};
+      llg_solve(he, kap, d, b, Ms, mn);
+      for (int q3 = 0; q3 < 3; ++q3) {
+        m.b[q3][t] = b[q3];
+        m.d[q3][t] = d[q3];
+      }
+    }
     const T hv = (T)(q - mn[f]);
-    F.A[f][c] = hv;
+    tri(F.A)(f)[c] = hv;
     log_iterate(m, 1, t, D(hv), err);
     for (int q3 = 0; q3 < 3; ++q3) {
       const unsigned long long bb = rbits(fabs(mn[q3] - ms[q3]) / Ms);
       rb = bb > rb ? bb : rb;
-      m.b[q3][t] = b[q3];
-      m.d[q3][t] = d[q3];
       m.M[q3][t] = mn[q3];
     }
     m.q[t] = q;
   }
-  rb = block_max_u64(rb);
-  if (threadIdx.x == 0 && rb) atomicMax(&C.cur[1], rb);
+  publish_residual(C, 1, rb);
 }
 
 // Iteration r >= 2 as an ordinary launch.  Every thread evaluates the
@@ -519,16 +694,15 @@ __global__ __launch_bounds__(256) void hm_step(Geo g, Fields<T> F, Mag m, double
                                               double H0z, Ctl C, int r, int* err) {
   if (load_u64(&C.cur[0]) != 0ull) return;
   bool bad;
-  if (stop_after(C, r - 1, bad)) {
+  if (stop_rule(C, r - 1, residual_bits(C, r - 1), bad)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) C.cur[0] = (unsigned long long)(r - 1);
     return;
   }
-  T* const* prev = (r & 1) ? F.H : F.A;
-  T* const* out = (r & 1) ? F.A : F.H;
-  unsigned long long lb = iterate_faces(g, m, F, prev, out, blockIdx.x * blockDim.x + threadIdx.x,
-                                        gridDim.x * blockDim.x, H0x, H0y, H0z, r, err);
-  lb = block_max_u64(lb);
-  if (threadIdx.x == 0 && lb) atomicMax(&C.cur[r], lb);
+  const Tri<T> prev = (r & 1) ? tri(F.H) : tri(F.A);
+  const Tri<T> out = (r & 1) ? tri(F.A) : tri(F.H);
+  const unsigned long long lb = iterate_faces(g, m, F, prev, out, blockIdx.x * blockDim.x + threadIdx.x,
+                                              gridDim.x * blockDim.x, H0x, H0y, H0z, r, err);
+  publish_residual(C, r, lb);
 }
 
 // Bounded-spin barrier across the (small, co-resident) grid of hm_finish.
@@ -573,12 +747,11 @@ __global__ __launch_bounds__(256) void hm_finish(Geo g, Fields<T> F, Mag m, doub
   bool bad = false;
   int r = r_next;
   for (;;) {
-    if (stop_after(C, r - 1, bad)) break;
-    T* const* prev = (r & 1) ? F.H : F.A;
-    T* const* out = (r & 1) ? F.A : F.H;
-    unsigned long long lb = iterate_faces(g, m, F, prev, out, tid, nth, H0x, H0y, H0z, r, err);
-    lb = block_max_u64(lb);
-    if (threadIdx.x == 0 && lb) atomicMax(&C.cur[r], lb);
+    if (stop_rule(C, r - 1, residual_bits(C, r - 1), bad)) break;
+    const Tri<T> prev = (r & 1) ? tri(F.H) : tri(F.A);
+    const Tri<T> out = (r & 1) ? tri(F.A) : tri(F.H);
+    const unsigned long long lb = iterate_faces(g, m, F, prev, out, tid, nth, H0x, H0y, H0z, r, err);
+    publish_residual(C, r, lb);
     if (!grid_barrier(bar)) {
       if (threadIdx.x == 0) atomicOr(err, 4);
       r += 1;
@@ -591,7 +764,7 @@ __global__ __launch_bounds__(256) void hm_finish(Geo g, Fields<T> F, Mag m, doub
 
 // End of a sub-step: bring the final magnetic H into H when it sits in A
 // (odd count), record the count and the sticky flags, and clear the other
-// sub-step's control block.
+// sub-step's final count.
 template <typename T>
 __global__ __launch_bounds__(256) void hm_commit(Fields<T> F, Mag m, Ctl C, int* iters_out, int* ring,
                                                 int* err) {
@@ -600,19 +773,21 @@ __global__ __launch_bounds__(256) void hm_commit(Fields<T> F, Mag m, Ctl C, int*
   if (rfin & 1)
     for (int t = tid; t < m.n; t += gridDim.x * blockDim.x) {
       const int f = face_family(m, t);
-      F.H[f][m.idx[t]] = F.A[f][m.idx[t]];
+      const int c = m.idx[t];
+      tri(F.H)(f)[c] = tri(F.A)(f)[c];
     }
   if (blockIdx.x == 0) {
-    for (int s2 = threadIdx.x; s2 < C.nres; s2 += blockDim.x) C.next[s2] = 0ull;
+    const unsigned long long bits = residual_bits(C, rfin);
     if (threadIdx.x == 0) {
+      C.next[0] = 0ull;
       iters_out[0] = rfin;
       ring[0] = rfin;
       bool bad;
-      stop_after(C, rfin, bad);
+      stop_rule(C, rfin, bits, bad);
       int e = 0;
       if (bad) e |= 2;
       else if (C.fixed_iter <= 0) {
-        const double rv = __longlong_as_double((long long)load_u64(&C.cur[rfin]));
+        const double rv = __longlong_as_double((long long)bits);
         if (!(rv < C.tol)) e |= 1;
       }
       if (e) atomicOr(err, e);
@@ -623,32 +798,88 @@ __global__ __launch_bounds__(256) void hm_commit(Fields<T> F, Mag m, Ctl C, int*
 // ---------------------------------------------------------------------------
 // Probes (FP64 accumulation).
 // ---------------------------------------------------------------------------
+
+// Within a multi-step run the tiles that take the fused two-half-step H
+// update hold H^{n+1/2} when the probes of level n+1 are taken.  Lag tells
+// the probes which tiles those are (far[tile] != 0; far == null: none) and
+// how h_bulk would have advanced them.
+template <typename T>
+struct Lag {
+  const unsigned char* far;
+  const T* mu;    // cell mu_r, or null when mu_r = 1 everywhere
+  T coef0, h;     // dt / (2 mu0) and dt / 2
+  int gx, gy, kc;
+};
+
+// H at face (f, i, j, k) at the probe level: the stored value, or for a
+// lagging tile the Faraday half step with the current E applied to it with
+// exactly the arithmetic of h_bulk (so the probe sees the value a separate
+// half-step pass would have stored).
+template <typename T>
+__device__ double h_level(const Geo& g, const Fields<T>& F, const Lag<T>& L, int f, int i, int j, int k) {
+  const int c = at(g, i, j, k);
+  const T hv = tri(F.H)(f)[c];
+  if (!L.far || i >= g.nx || j >= g.ny || k >= g.nz) return D(hv);
+  if (!L.far[(i >> 6) + L.gx * ((j >> 2) + L.gy * (k / L.kc))]) return D(hv);
+  const bool pxp = g.per & 1, pyp = g.per & 2, pzp = g.per & 4;
+  const T idx = (T)g.idx, idy = (T)g.idy, idz = (T)g.idz;
+  const T sdx = (T)g.dx, sdy = (T)g.dy, sdz = (T)g.dz;
+  const T mu0 = (T)kMu0, half = (T)0.5;
+  const T* Ex = F.E[0];
+  const T* Ey = F.E[1];
+  const T* Ez = F.E[2];
+  T curl, cf = L.coef0;
+  if (f == 0) {
+    if (!(pxp || i >= 1)) return D(hv);
+    const int jp = up(j, g.ny, pyp), kp = up(k, g.nz, pzp);
+    curl = dq(Ez[at(g, i, jp, k)] - Ez[c], sdy, idy) - dq(Ey[at(g, i, j, kp)] - Ey[c], sdz, idz);
+    if (L.mu) cf = L.h / (mu0 * (half * (L.mu[at(g, dn(i, g.nx, pxp), j, k)] + L.mu[c])));
+  } else if (f == 1) {
+    if (!(pyp || j >= 1)) return D(hv);
+    const int ip = up(i, g.nx, pxp), kp = up(k, g.nz, pzp);
+    curl = dq(Ex[at(g, i, j, kp)] - Ex[c], sdz, idz) - dq(Ez[at(g, ip, j, k)] - Ez[c], sdx, idx);
+    if (L.mu) cf = L.h / (mu0 * (half * (L.mu[at(g, i, dn(j, g.ny, pyp), k)] + L.mu[c])));
+  } else {
+    if (!(pzp || k >= 1)) return D(hv);
+    const int ip = up(i, g.nx, pxp), jp = up(j, g.ny, pyp);
+    curl = dq(Ey[at(g, ip, j, k)] - Ey[c], sdx, idx) - dq(Ex[at(g, i, jp, k)] - Ex[c], sdy, idy);
+    if (L.mu) cf = L.h / (mu0 * (half * (L.mu[at(g, i, j, dn(k, g.nz, pzp))] + L.mu[c])));
+  }
+  return D((T)(hv - cf * curl));
+}
+
 struct PointProbe {
   int slot;             // series row
   const void* h;        // field array (T) or null
   const double* mcomp;  // compact M component or null
   int ih, im;           // indices
   double ch, cm;        // value = ch * h[ih] + cm * mcomp[im]
+  int fam;              // h is H of this face family (read at the probe level), or -1
+  int pi, pj, pk;       // (i, j, k) of entry ih
 };
 
 template <typename T>
-__global__ void probe_points(const PointProbe* __restrict__ pp, int np, double* __restrict__ series,
-                            size_t cap, double* __restrict__ sums, long step, double dt) {
+__global__ void probe_points(Geo g, Fields<T> F, Lag<T> L, const PointProbe* __restrict__ pp, int np,
+                            double* __restrict__ series, size_t cap, double* __restrict__ sums, long step,
+                            double dt) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= np) return;
   const PointProbe q = pp[p];
   double v = 0.0;
-  if (q.h) v += q.ch * D(((const T*)q.h)[q.ih]);
+  if (q.h) {
+    const double hv = q.fam >= 0 ? h_level(g, F, L, q.fam, q.pi, q.pj, q.pk) : D(((const T*)q.h)[q.ih]);
+    v += q.ch * hv;
+  }
   if (q.mcomp) v += q.cm * q.mcomp[q.im];
   series[(size_t)q.slot * cap + step] = v;
   sums[q.slot] += dt * v;
 }
 
 // Poynting flux through the node plane x = i0: deterministic two-level sum
-// (fixed per-thread strides, fixed tree, partials combined in block order by
-// the last block to finish).
+// (fixed per-thread strides, a fixed tree per block, and the block partials
+// combined by the same fixed tree by whichever block finishes last).
 template <typename T>
-__global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, const int* __restrict__ planes,
+__global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, Lag<T> L, const int* __restrict__ planes,
                                                  const int* __restrict__ slots, double* __restrict__ partial,
                                                  unsigned int* __restrict__ ticket,
                                                  double* __restrict__ series, size_t cap,
@@ -664,26 +895,29 @@ __global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, const int*
   double s1 = 0.0, s2 = 0.0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n1; e += nb * blockDim.x) {
     const int k = e / g.ny, j = e - k * g.ny;
-    const double hz = 0.5 * (D(F.H[2][at(g, im, j, k)]) + D(F.H[2][at(g, i0, j, k)]));
+    const double hz = 0.5 * (h_level(g, F, L, 2, im, j, k) + h_level(g, F, L, 2, i0, j, k));
     s1 += D(F.E[1][at(g, i0, j, k)]) * hz;
   }
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += nb * blockDim.x) {
     const int k = e / NY, j = e - k * NY;
-    const double hy = 0.5 * (D(F.H[1][at(g, im, j, k)]) + D(F.H[1][at(g, i0, j, k)]));
+    const double hy = 0.5 * (h_level(g, F, L, 1, im, j, k) + h_level(g, F, L, 1, i0, j, k));
     s2 += D(F.E[2][at(g, i0, j, k)]) * hy;
   }
   __shared__ double r1[256], r2[256];
+  __shared__ bool last;
+  auto tree = [&]() {
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        r1[threadIdx.x] += r1[threadIdx.x + w];
+        r2[threadIdx.x] += r2[threadIdx.x + w];
+      }
+      __syncthreads();
+    }
+  };
   r1[threadIdx.x] = s1;
   r2[threadIdx.x] = s2;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      r1[threadIdx.x] += r1[threadIdx.x + w];
-      r2[threadIdx.x] += r2[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  __shared__ bool last;
+  tree();
   if (threadIdx.x == 0) {
     partial[(size_t)p * 2 * nb + 2 * blockIdx.x] = r1[0];
     partial[(size_t)p * 2 * nb + 2 * blockIdx.x + 1] = r2[0];
@@ -692,15 +926,20 @@ __global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, const int*
     last = (tk == (unsigned)nb - 1);
   }
   __syncthreads();
-  if (last && threadIdx.x == 0) {
-    __threadfence();
-    double a = 0.0, b = 0.0;
-    const double* pp = partial + (size_t)p * 2 * nb;
-    for (int q = 0; q < nb; ++q) {
-      a += __hip_atomic_load(&pp[2 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      b += __hip_atomic_load(&pp[2 * q + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    const double P = dydz * (a - b);
+  if (!last) return;
+  __threadfence();
+  // nb <= blockDim.x: one partial per thread, then the fixed tree
+  const double* pp = partial + (size_t)p * 2 * nb;
+  double a = 0.0, b = 0.0;
+  if ((int)threadIdx.x < nb) {
+    a = __hip_atomic_load(&pp[2 * threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b = __hip_atomic_load(&pp[2 * threadIdx.x + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  r1[threadIdx.x] = a;
+  r2[threadIdx.x] = b;
+  tree();
+  if (threadIdx.x == 0) {
+    const double P = dydz * (r1[0] - r2[0]);
     series[(size_t)slots[p] * cap + step] = P;
     sums[slots[p]] += dt * P;
     ticket[p] = 0u;

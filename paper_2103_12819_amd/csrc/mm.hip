@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <unordered_map>
@@ -54,6 +55,7 @@ struct mm_ctx {
   size_t esz;  // bytes per field element
   double tol;
   int max_iter, fixed_iter;
+  int scheme;   // 2: iterative second-order sub-step; 1: first-order (Sec. 3.2.1)
   double H0[3];
   hipStream_t stream;
   void* (*ualloc)(size_t, void*);
@@ -70,6 +72,9 @@ struct mm_ctx {
   void* eps;
   void* sig;
   void* mu;
+  unsigned char* mat;   // per-cell id into mtab (e_update), or null: dense maps
+  void* mtab;           // 256 eps_r then 256 sigma values (T)
+  int nmat;
 
   // magnetic faces
   int nmag;     // evolving faces (families contiguous)
@@ -83,7 +88,8 @@ struct mm_ctx {
   double *d_b[3], *d_d[3], *d_q;
   unsigned char* d_nbm;       // neighbour masks of the evolving faces
   void* A[3];                 // shadow H (ping-pong partner of H on magnetic faces)
-  unsigned long long* d_res;  // 2 control blocks of nres slots (slot 0: final count)
+  unsigned long long* d_res;  // final iteration count of the two sub-step parities
+  unsigned long long* d_part; // residual partials: 2 parities x nres iterations x step_blocks
   int nres;
   unsigned int* d_bar;        // barrier state of hm_finish
   int step_blocks, fin_blocks;
@@ -125,10 +131,20 @@ struct mm_ctx {
   int hlog_cap;
   bool adj_recompute;         // true while the adjoint recomputes a segment (no probes)
   int ckpt_every;             // 0: adjoint disabled
+  int ckpt_inner;             // inner checkpoint spacing of the adjoint (0: single level)
   std::vector<void*> ckpts;   // one device block per checkpoint
   AdjWork* adjw;
   std::vector<FaceCells> fcells;   // per magnetic face (evolving first)
   std::vector<bool> cell_mag;      // Ms > 0 per cell
+
+  // bulk tiles (64 x 4 columns x tkc planes; see mmk::Tiles): every tile,
+  // the tiles near evolving magnetic faces (those faces and every face
+  // their H_eff reads), and the rest ("far": fused H half steps)
+  int tgx, tgy, tgz, tkc;
+  int *d_tl_all, *d_tl_near, *d_tl_far;
+  int n_all, n_near, n_far;
+  unsigned char* d_far;      // per tile id: 1 if far
+  long long cells_near, cells_far;
 
   // optional kernel timing (mm_profile)
   bool prof;
@@ -242,6 +258,51 @@ mm_status upload_cellmap(mm_ctx* c, const double* src, double def, void** dst) {
   *dst = dalloc(c, c->nelem * sizeof(T));
   if (!*dst) return fail(c, MM_ENOMEM, "device allocation of a cell map failed");
   HIPCHECK(c, hipMemcpy(*dst, h.data(), c->nelem * sizeof(T), hipMemcpyHostToDevice));
+  return MM_OK;
+}
+
+// Byte material ids for the E update when the grid holds at most 256
+// distinct (eps_r, sigma) pairs (after conversion to the storage type, so
+// the table holds exactly the values of the dense maps); otherwise none.
+template <typename T>
+mm_status build_material_ids(mm_ctx* c, const mm_materials* mat) {
+  c->mat = nullptr;
+  c->mtab = nullptr;
+  c->nmat = 0;
+  std::vector<unsigned char> ids(c->nelem, 0);
+  std::vector<T> tab(512, (T)0);
+  std::unordered_map<uint64_t, int> seen;
+  auto bits = [](T v) {
+    uint64_t b = 0;
+    std::memcpy(&b, &v, sizeof(T));
+    return b;
+  };
+  for (int k = 0; k < c->nz; ++k)
+    for (int j = 0; j < c->ny; ++j)
+      for (int i = 0; i < c->nx; ++i) {
+        const T e = (T)cell(mat->eps_r, 1.0, c, i, j, k);
+        const T sg = (T)cell(mat->sigma, 0.0, c, i, j, k);
+        const uint64_t key = bits(e) * 0x9E3779B97F4A7C15ull ^ bits(sg);
+        auto it = seen.find(key);
+        int id;
+        if (it == seen.end()) {
+          id = (int)seen.size();
+          if (id >= 256) return MM_OK;   // too many: dense maps
+          seen.emplace(key, id);
+          tab[id] = e;
+          tab[256 + id] = sg;
+        } else {
+          id = it->second;
+          if (bits(tab[id]) != bits(e) || bits(tab[256 + id]) != bits(sg)) return MM_OK;  // key clash: dense
+        }
+        ids[pidx(c, i, j, k)] = (unsigned char)id;
+      }
+  c->mat = (unsigned char*)dalloc(c, c->nelem);
+  c->mtab = dalloc(c, 512 * sizeof(T));
+  if (!c->mat || !c->mtab) return fail(c, MM_ENOMEM, "material-id allocation failed");
+  HIPCHECK(c, hipMemcpy(c->mat, ids.data(), c->nelem, hipMemcpyHostToDevice));
+  HIPCHECK(c, hipMemcpy(c->mtab, tab.data(), 512 * sizeof(T), hipMemcpyHostToDevice));
+  c->nmat = (int)seen.size();
   return MM_OK;
 }
 
@@ -393,6 +454,24 @@ mmk::Mag make_mag(const mm_ctx* c) {
   return m;
 }
 
+mmk::Tiles tiles(const mm_ctx* c, const int* list, int split = 1) {
+  mmk::Tiles t;
+  t.list = list;
+  t.gx = c->tgx;
+  t.gy = c->tgy;
+  t.kc = c->tkc;
+  t.split = split;
+  return t;
+}
+
+// z-split for a launch over n tiles: enough blocks to fill the chip
+// (~2048), runs of at least 4 planes.
+int split_for(const mm_ctx* c, int n) {
+  if (n <= 0) return 1;
+  const int want = (2048 + n - 1) / n;
+  return std::max(1, std::min(want, c->tkc / 4));
+}
+
 int kchunk_for(const mm_ctx* c, dim3& grid) {
   const int gx = (c->nx + 63) / 64, gy = (c->ny + 3) / 4;
   // aim for >= ~4096 blocks while keeping each z run long enough to reuse
@@ -415,16 +494,19 @@ int iterations_to_enqueue(const mm_ctx* c) {
   return std::max(1, std::min(std::min(mx + 1, 32), c->max_iter));
 }
 
+// One H-M sub-step.  near_only: the Faraday half step runs on the near
+// tiles only (the far tiles take it inside the fused pass of h_far).
 template <typename T>
-mm_status substep(mm_ctx* c) {
+mm_status substep(mm_ctx* c, bool near_only = false) {
   Geo g = make_geo(c);
   mmk::Fields<T> F = make_fields<T>(c);
   const double h = 0.5 * c->dt;
   const double hmu0 = h / mmk::kMu0;
   mmk::Ctl C;
-  C.cur = c->d_res + (size_t)(c->substep & 1) * c->nres;
-  C.next = c->d_res + (size_t)((c->substep + 1) & 1) * c->nres;
-  C.nres = c->nres;
+  C.cur = c->d_res + (c->substep & 1);
+  C.next = c->d_res + ((c->substep + 1) & 1);
+  C.P = c->step_blocks;
+  C.part = c->d_part + (size_t)(c->substep & 1) * c->nres * c->step_blocks;
   C.tol = c->tol;
   C.max_iter = c->max_iter;
   C.fixed_iter = c->fixed_iter;
@@ -432,22 +514,23 @@ mm_status substep(mm_ctx* c) {
   if (c->nmag > 0) {
     mmk::Mag m = make_mag(c);
     Timed tm(c, 2);
-    hipLaunchKernelGGL((mmk::hm_pre<T>), dim3((c->nmag + 255) / 256), dim3(256), 0, c->stream, g, F, m, hmu0,
-                       H0x, H0y, H0z, C, c->d_err);
+    hipLaunchKernelGGL((mmk::hm_pre<T>), dim3(c->step_blocks), dim3(256), 0, c->stream, g, F, m, h, hmu0,
+                       H0x, H0y, H0z, c->scheme == 1 ? 1 : 0, C, c->d_err);
   }
   HIPCHECK(c, hipGetLastError());
-  dim3 grid;
-  const int kc = kchunk_for(c, grid);
-  {
+  const int nt = near_only ? c->n_near : c->n_all;
+  if (nt > 0) {
+    const int split = split_for(c, nt);
+    const mmk::Tiles tl = tiles(c, near_only ? c->d_tl_near : c->d_tl_all, split);
     Timed tm(c, 1);
     if (c->mu)
-      hipLaunchKernelGGL((mmk::h_bulk<T, true>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->H[0], (T*)c->H[1],
-                         (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2], (const T*)c->mu,
-                         (T)hmu0, (T)h, kc);
+      hipLaunchKernelGGL((mmk::h_bulk<T, true, 1>), dim3(nt * split), dim3(64, 4), 0, c->stream, g, (T*)c->H[0],
+                         (T*)c->H[1], (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2],
+                         (const T*)c->mu, (T)hmu0, (T)h, tl);
     else
-      hipLaunchKernelGGL((mmk::h_bulk<T, false>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->H[0], (T*)c->H[1],
-                         (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2], (const T*)c->mu,
-                         (T)hmu0, (T)h, kc);
+      hipLaunchKernelGGL((mmk::h_bulk<T, false, 1>), dim3(nt * split), dim3(64, 4), 0, c->stream, g, (T*)c->H[0],
+                         (T*)c->H[1], (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2],
+                         (const T*)c->mu, (T)hmu0, (T)h, tl);
   }
   HIPCHECK(c, hipGetLastError());
   if (c->nmag > 0) {
@@ -495,36 +578,70 @@ mmk::Src make_src(const mm_ctx* c) {
 template <typename T>
 mm_status e_step(mm_ctx* c) {
   const Geo g = make_geo(c);
-  dim3 grid;
-  const int kc = kchunk_for(c, grid);
+  const mmk::Tiles tl = tiles(c, c->d_tl_all);
   const mmk::Src src = make_src(c);
   Timed tm(c, 0);
-  if (c->sig)
-    hipLaunchKernelGGL((mmk::e_update<T, true>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->E[0], (T*)c->E[1],
-                       (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], (const T*)c->eps,
-                       (const T*)c->sig, (T)c->dt, src, kc);
+#define MM_EUPD(SIG, MAT)                                                                                      \
+  hipLaunchKernelGGL((mmk::e_update<T, SIG, MAT>), dim3(c->n_all), dim3(64, 4), 0, c->stream, g, (T*)c->E[0], \
+                     (T*)c->E[1], (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2],       \
+                     (const T*)c->eps, (const T*)c->sig, c->mat, (const T*)c->mtab, (T)c->dt, src, tl)
+  if (c->mat) {
+    if (c->sig) MM_EUPD(true, true);
+    else MM_EUPD(false, true);
+  } else {
+    if (c->sig) MM_EUPD(true, false);
+    else MM_EUPD(false, false);
+  }
+#undef MM_EUPD
+  HIPCHECK(c, hipGetLastError());
+  return MM_OK;
+}
+
+// The fused Faraday pass of the far tiles: Step 3 of step n and Step 1 of
+// step n+1 (both with curl E^{n+1}), H^{n+1/2} -> H^{n+3/2}.
+template <typename T>
+mm_status h_far(mm_ctx* c) {
+  if (c->n_far == 0) return MM_OK;
+  const Geo g = make_geo(c);
+  const mmk::Tiles tl = tiles(c, c->d_tl_far);
+  const double h = 0.5 * c->dt, hmu0 = h / mmk::kMu0;
+  Timed tm(c, 7);
+  if (c->mu)
+    hipLaunchKernelGGL((mmk::h_bulk<T, true, 2>), dim3(c->n_far), dim3(64, 4), 0, c->stream, g, (T*)c->H[0],
+                       (T*)c->H[1], (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2],
+                       (const T*)c->mu, (T)hmu0, (T)h, tl);
   else
-    hipLaunchKernelGGL((mmk::e_update<T, false>), grid, dim3(64, 4), 0, c->stream, g, (T*)c->E[0], (T*)c->E[1],
-                       (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], (const T*)c->eps,
-                       (const T*)c->sig, (T)c->dt, src, kc);
+    hipLaunchKernelGGL((mmk::h_bulk<T, false, 2>), dim3(c->n_far), dim3(64, 4), 0, c->stream, g, (T*)c->H[0],
+                       (T*)c->H[1], (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2],
+                       (const T*)c->mu, (T)hmu0, (T)h, tl);
   HIPCHECK(c, hipGetLastError());
   return MM_OK;
 }
 
 // Probe sampling at level c->step + 1.
+// lagged: the far tiles hold H^{n+1/2} (the fused pass comes after).
 template <typename T>
-mm_status record_probes(mm_ctx* c) {
+mm_status record_probes(mm_ctx* c, bool lagged = false) {
   if (c->adj_recompute) return MM_OK;
   const Geo g = make_geo(c);
+  const mmk::Fields<T> F = make_fields<T>(c);
+  mmk::Lag<T> L;
+  L.far = (lagged && c->n_far > 0) ? c->d_far : nullptr;
+  L.mu = (const T*)c->mu;
+  L.h = (T)(0.5 * c->dt);
+  L.coef0 = (T)(0.5 * c->dt / mmk::kMu0);
+  L.gx = c->tgx;
+  L.gy = c->tgy;
+  L.kc = c->tkc;
   Timed tm(c, 5);
   if (c->npoints)
-    hipLaunchKernelGGL((mmk::probe_points<T>), dim3((c->npoints + 63) / 64), dim3(64), 0, c->stream, c->d_points,
-                       c->npoints, c->d_series, c->series_cap, c->d_sums, c->step, c->dt);
+    hipLaunchKernelGGL((mmk::probe_points<T>), dim3((c->npoints + 63) / 64), dim3(64), 0, c->stream, g, F, L,
+                       c->d_points, c->npoints, c->d_series, c->series_cap, c->d_sums, c->step, c->dt);
   if (c->nflux) {
     const int NY = nodes(c, 1), NZ = nodes(c, 2);
-    hipLaunchKernelGGL((mmk::probe_flux<T>), dim3(c->flux_blocks, c->nflux), dim3(256), 0, c->stream, g,
-                       make_fields<T>(c), c->d_planes, c->d_slots, c->d_partial, c->d_ticket, c->d_series,
-                       c->series_cap, c->d_sums, c->step, c->dt, c->dy * c->dz, NY, NZ);
+    hipLaunchKernelGGL((mmk::probe_flux<T>), dim3(c->flux_blocks, c->nflux), dim3(256), 0, c->stream, g, F, L,
+                       c->d_planes, c->d_slots, c->d_partial, c->d_ticket, c->d_series, c->series_cap,
+                       c->d_sums, c->step, c->dt, c->dy * c->dz, NY, NZ);
   }
   HIPCHECK(c, hipGetLastError());
   return MM_OK;
@@ -541,6 +658,34 @@ mm_status one_step(mm_ctx* c) {
   s = record_probes<T>(c);
   if (s) return s;
   c->step++;
+  return MM_OK;
+}
+
+mm_status save_checkpoint(mm_ctx* c, size_t idx);
+
+// n steps with the far tiles' half steps fused across step boundaries.
+// Step q starts a chain when the far tiles are at an integer level (first
+// step of the call) and ends one when it must leave them there (last step,
+// or a checkpoint before the next step); inside a chain the far tiles skip
+// Step 1 and Step 3 and take the fused pass after the probes instead.
+template <typename T>
+mm_status run_steps(mm_ctx* c, int64_t n) {
+  mm_status s;
+  bool lagging = false;   // far tiles hold H^{n+1/2} of the current step
+  for (int64_t q = 0; q < n; ++q) {
+    if (c->ckpt_every > 0 && c->step % c->ckpt_every == 0) {
+      s = save_checkpoint(c, (size_t)(c->step / c->ckpt_every));
+      if (s) return s;
+    }
+    const bool end = q == n - 1 || (c->ckpt_every > 0 && (c->step + 1) % c->ckpt_every == 0);
+    if ((s = substep<T>(c, lagging))) return s;     // Step 1
+    if ((s = e_step<T>(c))) return s;               // Step 2
+    if ((s = substep<T>(c, !end))) return s;        // Step 3
+    if ((s = record_probes<T>(c, !end))) return s;
+    if (!end && (s = h_far<T>(c))) return s;
+    lagging = !end;
+    c->step++;
+  }
   return MM_OK;
 }
 
@@ -575,6 +720,86 @@ bool finite_nonneg(const double* a, size_t n, bool strictly_positive) {
   return true;
 }
 
+// Launch order of a set of tiles: the dispatcher sends block b to XCD
+// b mod 8, so the tiles (in natural order, x fastest) are cut into 8 runs
+// of near-equal length and the runs interleaved; each XCD then works on a
+// compact slab and the x and y halos its blocks share stay in its L2.
+std::vector<int> xcd_order(const std::vector<int>& nat) {
+  const size_t n = nat.size(), P = (n + 7) / 8;
+  std::vector<int> out;
+  out.reserve(n);
+  for (size_t q = 0; q < P; ++q)
+    for (size_t x = 0; x < 8; ++x) {
+      const size_t at = x * P + q;
+      if (at < std::min(n, (x + 1) * P)) out.push_back(nat[at]);
+    }
+  return out;
+}
+
+// Tile grid of the bulk kernels and its near/far split.  A tile is near
+// when it holds an evolving magnetic face or a face that such a face's
+// H_eff reads (all within one cell of it, wrapped on periodic axes).
+mm_status build_tiles(mm_ctx* c) {
+  c->tgx = (c->nx + 63) / 64;
+  c->tgy = (c->ny + 3) / 4;
+  const int chunks = std::max(1, 4096 / std::max(1, c->tgx * c->tgy));
+  c->tkc = std::min(std::max(4, (c->nz + chunks - 1) / chunks), c->nz);
+  c->tgz = (c->nz + c->tkc - 1) / c->tkc;
+  const size_t nt = (size_t)c->tgx * c->tgy * c->tgz;
+  std::vector<unsigned char> near(nt, 0);
+  const int n3[3] = {c->nx, c->ny, c->nz};
+  for (size_t t = 0; t < (size_t)c->nmag; ++t) {
+    const int pi = c->h_idx[t];
+    const int k = pi / (c->px * c->py), rr = pi - k * c->px * c->py, j = rr / c->px, i = rr - j * c->px;
+    const int p0[3] = {i, j, k};
+    for (int dk = -1; dk <= 1; ++dk)
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          int q[3] = {p0[0] + di, p0[1] + dj, p0[2] + dk};
+          bool ok = true;
+          for (int a = 0; a < 3; ++a) {
+            if (c->per >> a & 1) q[a] = (q[a] + n3[a]) % n3[a];
+            else if (q[a] < 0 || q[a] >= n3[a]) ok = false;
+          }
+          if (ok) near[(q[0] / 64) + (size_t)c->tgx * ((q[1] / 4) + (size_t)c->tgy * (q[2] / c->tkc))] = 1;
+        }
+  }
+  std::vector<int> all, nr, fr;
+  std::vector<unsigned char> far(nt, 0);
+  c->cells_near = c->cells_far = 0;
+  for (size_t id = 0; id < nt; ++id) {
+    all.push_back((int)id);
+    const int bx = (int)(id % c->tgx), by = (int)((id / c->tgx) % c->tgy), bz = (int)(id / ((size_t)c->tgx * c->tgy));
+    const long long cells = (long long)std::min(64, c->nx - 64 * bx) * std::min(4, c->ny - 4 * by) *
+                            std::min(c->tkc, c->nz - c->tkc * bz);
+    if (near[id]) {
+      nr.push_back((int)id);
+      c->cells_near += cells;
+    } else {
+      fr.push_back((int)id);
+      far[id] = 1;
+      c->cells_far += cells;
+    }
+  }
+  all = xcd_order(all);
+  nr = xcd_order(nr);
+  fr = xcd_order(fr);
+  c->n_all = (int)all.size();
+  c->n_near = (int)nr.size();
+  c->n_far = (int)fr.size();
+  c->d_tl_all = (int*)dalloc(c, all.size() * sizeof(int));
+  c->d_tl_near = (int*)dalloc(c, nr.size() * sizeof(int));
+  c->d_tl_far = (int*)dalloc(c, fr.size() * sizeof(int));
+  c->d_far = (unsigned char*)dalloc(c, nt);
+  if (!c->d_tl_all || !c->d_tl_near || !c->d_tl_far || !c->d_far)
+    return fail(c, MM_ENOMEM, "tile-list allocation failed");
+  HIPCHECK(c, hipMemcpy(c->d_tl_all, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice));
+  if (!nr.empty()) HIPCHECK(c, hipMemcpy(c->d_tl_near, nr.data(), nr.size() * sizeof(int), hipMemcpyHostToDevice));
+  if (!fr.empty()) HIPCHECK(c, hipMemcpy(c->d_tl_far, fr.data(), fr.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHECK(c, hipMemcpy(c->d_far, far.data(), nt, hipMemcpyHostToDevice));
+  return MM_OK;
+}
+
 mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
   const size_t ncells = (size_t)c->nx * c->ny * c->nz;
   const bool fp32 = c->prec == MM_FP32;
@@ -603,6 +828,8 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
     s = fp32 ? upload_cellmap<float>(c, mat->mu_r, 1.0, &c->mu) : upload_cellmap<double>(c, mat->mu_r, 1.0, &c->mu);
     if (s) return s;
   }
+  s = fp32 ? build_material_ids<float>(c, mat) : build_material_ids<double>(c, mat);
+  if (s) return s;
 
   // magnetic faces: Ms_f = mean of the 2 cells (a PEC wall face uses its one
   // cell); alpha_f, gamma_f over the magnetic cells only; M0_f = mean of
@@ -672,8 +899,16 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
           const double nrm = std::sqrt((M0[0] * M0[0] + M0[1] * M0[1]) + M0[2] * M0[2]);
           if (!(nrm > 0)) return fail(c, MM_EINVAL, "initial magnetisation averages to zero on a magnetic face");
           const double sc = Msf / nrm;
-          const double kap = mmk::kMu0 * gf * c->dt / 4.0;
-          const double vals[7] = {Msf, kap, af / Msf, M0[0] * sc, M0[1] * sc, M0[2] * sc, 0.0};
+          // per-face constants of the sub-step: kappa = mu0 gamma dt / 4 and
+          // alpha / Ms (eq:llg_tra5/6), or for the first-order scheme
+          // mu0 gamma_L and alpha mu0 gamma_L / Ms (eq:LLG_scalar)
+          double k1 = mmk::kMu0 * gf * c->dt / 4.0, k2 = af / Msf;
+          if (c->scheme == 1) {
+            const double gL = gf / (1.0 + af * af);
+            k1 = mmk::kMu0 * gL;
+            k2 = af * mmk::kMu0 * gL / Msf;
+          }
+          const double vals[7] = {Msf, k1, k2, M0[0] * sc, M0[1] * sc, M0[2] * sc, 0.0};
           const int pi = (int)pidx(c, i, j, k);
           FaceCells fcl;
           auto lin = [&](const int q[3]) {
@@ -790,16 +1025,7 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
       HIPCHECK(c, hipMemcpy(c->d_M[a], hv[3 + a].data(), ntot * sizeof(double), hipMemcpyHostToDevice));
   }
   c->nres = std::max(c->max_iter, c->fixed_iter) + 2;
-  c->d_res = (unsigned long long*)dalloc(c, 2 * (size_t)c->nres * sizeof(unsigned long long));
-  c->d_err = (int*)dalloc(c, sizeof(int));
-  c->d_bar = (unsigned int*)dalloc(c, 2 * sizeof(unsigned int));
-  if (!c->d_res || !c->d_err || !c->d_bar) return fail(c, MM_ENOMEM, "allocation failed");
-  HIPCHECK(c, hipMemset(c->d_res, 0, 2 * (size_t)c->nres * sizeof(unsigned long long)));
-  HIPCHECK(c, hipMemset(c->d_err, 0, sizeof(int)));
-  HIPCHECK(c, hipMemset(c->d_bar, 0, 2 * sizeof(unsigned int)));
-  HIPCHECK(c, hipHostMalloc((void**)&c->h_ring, 64 * sizeof(int), hipHostMallocMapped));
-  std::memset(c->h_ring, 0, 64 * sizeof(int));
-  HIPCHECK(c, hipHostGetDevicePointer((void**)&c->d_ring, c->h_ring, 0));
+  c->step_blocks = c->fin_blocks = 1;
   if (c->nmag > 0) {
     int dev = 0, ncu = 0;
     HIPCHECK(c, hipGetDevice(&dev));
@@ -807,6 +1033,23 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
     const int want = (c->nmag + 255) / 256;
     c->step_blocks = std::max(1, std::min(want, 8 * ncu));
     c->fin_blocks = std::max(1, std::min(want, ncu));
+  }
+  c->d_res = (unsigned long long*)dalloc(c, 2 * sizeof(unsigned long long));
+  c->d_part = (unsigned long long*)dalloc(c, 2 * (size_t)c->nres * c->step_blocks * sizeof(unsigned long long));
+  c->d_err = (int*)dalloc(c, sizeof(int));
+  c->d_bar = (unsigned int*)dalloc(c, 2 * sizeof(unsigned int));
+  if (!c->d_res || !c->d_part || !c->d_err || !c->d_bar) return fail(c, MM_ENOMEM, "allocation failed");
+  HIPCHECK(c, hipMemset(c->d_res, 0, 2 * sizeof(unsigned long long)));
+  HIPCHECK(c, hipMemset(c->d_part, 0, 2 * (size_t)c->nres * c->step_blocks * sizeof(unsigned long long)));
+  HIPCHECK(c, hipMemset(c->d_err, 0, sizeof(int)));
+  HIPCHECK(c, hipMemset(c->d_bar, 0, 2 * sizeof(unsigned int)));
+  HIPCHECK(c, hipHostMalloc((void**)&c->h_ring, 64 * sizeof(int), hipHostMallocMapped));
+  std::memset(c->h_ring, 0, 64 * sizeof(int));
+  HIPCHECK(c, hipHostGetDevicePointer((void**)&c->d_ring, c->h_ring, 0));
+
+  {
+    mm_status ts = build_tiles(c);
+    if (ts) return ts;
   }
 
   // soft source: J0 p over the bounding box of its nonzero interior edges
@@ -899,6 +1142,7 @@ mm_status mm_init(mm_ctx** out, const mm_grid* g, double dt, const mm_materials*
       opt->max_iter > 1000000)
     return bad("iteration options");
   if (opt->prec != MM_FP64 && opt->prec != MM_FP32) return bad("precision");
+  if (opt->scheme != 0 && opt->scheme != 1 && opt->scheme != 2) return bad("scheme");
   const size_t ncells = (size_t)g->nx * g->ny * g->nz;
   if (!finite_nonneg(mat->eps_r, ncells, true) || !finite_nonneg(mat->mu_r, ncells, true) ||
       !finite_nonneg(mat->sigma, ncells, false) || !finite_nonneg(mat->Ms, ncells, false) ||
@@ -934,6 +1178,8 @@ mm_status mm_init(mm_ctx** out, const mm_grid* g, double dt, const mm_materials*
   c->tol = opt->tol;
   c->max_iter = opt->max_iter;
   c->fixed_iter = opt->fixed_iter;
+  c->scheme = opt->scheme == 1 ? 1 : 2;
+  if (c->scheme == 1) c->fixed_iter = 1;   // one explicit update per sub-step
   for (int a = 0; a < 3; ++a) c->H0[a] = bias ? bias->H0[a] : 0.0;
   c->stream = (hipStream_t)opt->hip_stream;
   c->ualloc = opt->dev_alloc;
@@ -962,15 +1208,7 @@ mm_status mm_step(mm_ctx* c, int64_t n) {
   if (s) return s;
   s = grow_buffers(c, (size_t)(c->step + n));
   if (s) return s;
-  for (int64_t q = 0; q < n; ++q) {
-    if (c->ckpt_every > 0 && c->step % c->ckpt_every == 0) {
-      s = save_checkpoint(c, (size_t)(c->step / c->ckpt_every));
-      if (s) return s;
-    }
-    s = c->prec == MM_FP32 ? one_step<float>(c) : one_step<double>(c);
-    if (s) return s;
-  }
-  return MM_OK;
+  return c->prec == MM_FP32 ? run_steps<float>(c, n) : run_steps<double>(c, n);
 }
 
 mm_status mm_add_probe(mm_ctx* c, const mm_probe_desc* d, int32_t* id) {
@@ -990,6 +1228,12 @@ mm_status mm_add_probe(mm_ctx* c, const mm_probe_desc* d, int32_t* id) {
     if (d->i < 0 || d->j < 0 || d->k < 0 || d->i >= ext[0] || d->j >= ext[1] || d->k >= ext[2])
       return fail(c, MM_EINVAL, "probe index outside the field extent");
     const int pi = (int)pidx(c, d->i, d->j, d->k);
+    r.pp.fam = -1;
+    r.pp.pi = d->i;
+    r.pp.pj = d->j;
+    r.pp.pk = d->k;
+    if (d->field >= 3 && d->field < 6) r.pp.fam = d->field - 3;
+    if (d->field >= 15) r.pp.fam = d->field - 15;
     if (d->field < 6) {
       r.pp.h = d->field < 3 ? c->E[d->field] : c->H[d->field - 3];
       r.pp.ih = pi;
@@ -1217,12 +1461,29 @@ mm_status mm_info(const mm_ctx* c, int64_t out[8]) {
   return MM_OK;
 }
 
-mm_status mm_adjoint_enable(mm_ctx* c, int32_t checkpoint_every) {
+mm_status mm_layout(const mm_ctx* c, int64_t out[8]) {
+  if (!c || !out) return MM_EINVAL;
+  out[0] = c->n_all;
+  out[1] = c->n_near;
+  out[2] = c->n_far;
+  out[3] = c->cells_near;
+  out[4] = c->cells_far;
+  out[5] = c->tkc;
+  out[6] = c->nmat;
+  out[7] = 0;
+  return MM_OK;
+}
+
+mm_status mm_adjoint_enable(mm_ctx* c, int32_t checkpoint_every, int32_t inner_every) {
   if (!c) return MM_EINVAL;
   if (checkpoint_every < 1) return fail(c, MM_EINVAL, "checkpoint_every must be >= 1");
+  if (inner_every < 0 || inner_every > checkpoint_every)
+    return fail(c, MM_EINVAL, "inner_every must be in [0, checkpoint_every]");
   if (c->step != 0) return fail(c, MM_ESTATE, "the adjoint must be enabled before the first step");
   if (c->mu) return fail(c, MM_EINVAL, "the adjoint supports mu_r = 1 only");
+  if (c->scheme != 2) return fail(c, MM_EINVAL, "the adjoint supports the second-order scheme only");
   c->ckpt_every = checkpoint_every;
+  c->ckpt_inner = inner_every;
   return MM_OK;
 }
 

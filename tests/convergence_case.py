@@ -13,42 +13,18 @@ import math
 import numpy as np
 
 import workloads as W
-from oracle import Simulation
+from oracle import from_config
 
 L = 0.1
 
 
-def build(N, tol=1e-6, side=L):
+def build(N, tol=1e-6, side=L, scheme=2):
     """`side` is the edge length of the periodic cube centred on the origin."""
-    d = (side / N,) * 3
-    dt = W.cfl_dt(0.9, *d)
-    xn = np.arange(N) * d[0] - side / 2        # node coordinates
-    xc = xn + d[0] / 2                          # cell-centre coordinates
-    X, Y, Z = np.meshgrid(xc, xc, xc, indexing="ij")
-    g = np.exp(-1000.0 * (X**2 + Y**2 + Z**2))
-    host = lambda a: np.ascontiguousarray(a.transpose(2, 1, 0))
-    m0 = np.zeros((3, N, N, N))
-    m0[0] = 1.0
-    sim = Simulation((N,) * 3, d, dt, eps_r=host(1 + g), sigma=host(0.1 * g),
-                     Ms=host(1e4 * (1 + g)), alpha=host(0.5 * (1 + g)),
-                     gamma=host(-1.759e11 * (1 + g)), m0_dir=m0,
-                     periodic=(True, True, True), tol=tol, max_iter=100)
-    k = 20 * math.pi
-    e0, h0 = 1e6, 1e6 / (120 * math.pi)
-    ones = np.ones((N, N, N))
-    # ijk-indexed placements
-    Ex = e0 * np.cos(k * xn)[None, None, :] * ones      # cos(20 pi z), z at nodes
-    Ey = e0 * np.cos(k * xn)[:, None, None] * ones      # cos(20 pi x), x at nodes
-    Ez = e0 * np.cos(k * xn)[None, :, None] * ones      # cos(20 pi y), y at nodes
-    Hx = h0 * np.cos(k * xc)[None, :, None] * ones      # cos(20 pi y), y at cell centres
-    Hy = h0 * np.cos(k * xc)[None, None, :] * ones      # cos(20 pi z), z at cell centres
-    Hz = h0 * np.cos(k * xc)[:, None, None] * ones      # cos(20 pi x), x at cell centres
-    sim.set_fields(E=[host(a) for a in (Ex, Ey, Ez)], H=[host(a) for a in (Hx, Hy, Hz)])
-    return sim
+    return from_config(W.convergence_cube(N, side=side, tol=tol), with_probes=False, scheme=scheme)
 
 
-def run(N, side=L):
-    sim = build(N, side=side)
+def run(N, side=L, scheme=2):
+    sim = build(N, side=side, scheme=scheme)
     sim.step(5 * N // 32)
     out = {}
     for nm in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):

@@ -41,12 +41,12 @@ def test_struct_layouts_match_the_header():
     assert C.sizeof(N.mm_materials) == 7 * 8
     assert C.sizeof(N.mm_bias) == 24
     assert C.sizeof(N.mm_source) == 40
-    assert C.sizeof(N.mm_options) == 56
+    assert C.sizeof(N.mm_options) == 64
     assert C.sizeof(N.mm_probe_desc) == 20
 
 
 def _init(lib, n=(8, 4, 4), d=(1e-6,) * 3, dt=None, tol=1e-10, max_iter=10, prec=0, Ms=None,
-          eps=None, bc=(0, 0, 0)):
+          eps=None, bc=(0, 0, 0), scheme=0):
     ctx = C.c_void_p()
     g = N.mm_grid(n[0], n[1], n[2], (C.c_int32 * 3)(*bc), d[0], d[1], d[2])
     keep = [] if Ms is None else [Ms]
@@ -57,7 +57,7 @@ def _init(lib, n=(8, 4, 4), d=(1e-6,) * 3, dt=None, tol=1e-10, max_iter=10, prec
         keep.append(eps)
         mat.eps_r = eps.ctypes.data_as(C.POINTER(C.c_double))
     opt = N.mm_options()
-    opt.prec, opt.tol, opt.max_iter = prec, tol, max_iter
+    opt.prec, opt.tol, opt.max_iter, opt.scheme = prec, tol, max_iter, scheme
     if dt is None:
         dt = W.cfl_dt(0.9, *d)
     st = lib.mm_init(C.byref(ctx), C.byref(g), dt, C.byref(mat), None, None, C.byref(opt))
@@ -70,6 +70,7 @@ def _init(lib, n=(8, 4, 4), d=(1e-6,) * 3, dt=None, tol=1e-10, max_iter=10, prec
     dict(tol=0.0),
     dict(max_iter=0),
     dict(prec=7),
+    dict(scheme=3),
     dict(n=(0, 4, 4)),
     dict(d=(1e-6, 0.0, 1e-6), dt=1e-16),
     dict(bc=(0, 2, 0)),

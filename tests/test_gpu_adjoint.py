@@ -11,7 +11,7 @@ from tests import test_oracle_adjoint as OA
 pytestmark = pytest.mark.gpu
 
 
-def _gpu(ckpt, steps=OA.STEPS, fixed_iter=0, eps=None, Ms=None):
+def _gpu(ckpt, steps=OA.STEPS, fixed_iter=0, eps=None, Ms=None, inner=0):
     import paper_2103_12819_amd as mm
     e0, sig, ms0, alpha, m0, prof, E, H = OA._materials()
     dt = W.cfl_dt(0.9, *OA.D)
@@ -20,7 +20,7 @@ def _gpu(ckpt, steps=OA.STEPS, fixed_iter=0, eps=None, Ms=None):
                  source=(2, prof, 3e12, 1 / 3e12, 1e-12), tol=1e-13, max_iter=50, fixed_iter=fixed_iter)
     sim.set_fields(E=E, H=H)
     pid = sim.add_probe(1, 0, OA.I0)
-    sim.enable_adjoint(ckpt)
+    sim.enable_adjoint(ckpt, inner)
     sim.step(steps)
     return sim, pid
 
@@ -45,7 +45,10 @@ def test_gradient_matches_oracle_adjoint(oracle_grads):
 
 
 def test_checkpoint_spacing_does_not_change_the_gradient():
+    """Single-level spacings 10, 3, 1 and two-level (outer, inner) spacings
+    (10, 3), (10, 1), (4, 3) give bit-identical gradients."""
     sims = [_gpu(ckpt=k) for k in (OA.STEPS, 3, 1)]
+    sims += [_gpu(ckpt=k, inner=q) for k, q in ((OA.STEPS, 3), (OA.STEPS, 1), (4, 3))]
     grads = [s.adjoint(p) for s, p in sims]
     for g in grads[1:]:
         assert np.array_equal(g[0], grads[0][0]) and np.array_equal(g[1], grads[0][1])

@@ -323,6 +323,44 @@ def scale1024(seed: int = 0, steps: int = 500, n=(1024, 512, 512)) -> Config:
     return cfg
 
 
+def convergence_cube(N: int, side: float = 0.2, tol: float = 1e-6) -> Config:
+    """The coupled convergence problem of Sec. 5.1 on an N^3 grid.
+
+    Fully periodic cube of edge `side` centred on the origin; cosine E and H
+    of eq:convergeE / eq:convergeH (amplitudes 1e6 V/m and 1e6/(120 pi)
+    A/m, wavenumber 20 pi) at their Yee locations; Gaussian bumps
+    g = exp(-1000 r^2) at cell centres in sigma = 0.1 g, eps_r = 1 + g,
+    Ms = 1e4 (1 + g), alpha = 0.5 (1 + g), gamma = -1.759e11 (1 + g);
+    M along x, no bias; CFL 0.9 on the vacuum light speed; 5 N / 32 steps,
+    so every resolution reaches the same time.
+    """
+    d = (side / N,) * 3
+    xn = np.arange(N) * d[0] - side / 2        # node coordinates
+    xc = xn + d[0] / 2                          # cell-centre coordinates
+    X, Y, Z = np.meshgrid(xc, xc, xc, indexing="ij")
+    g = np.exp(-1000.0 * (X**2 + Y**2 + Z**2))
+    host = lambda a: np.ascontiguousarray(a.transpose(2, 1, 0))
+    m0 = np.zeros((3, N, N, N))
+    m0[0] = 1.0
+    cfg = Config(name=f"conv{N}", n=(N, N, N), d=d, dt=cfl_dt(0.9, *d), steps=5 * N // 32,
+                 periodic=(True, True, True), eps_r=host(1 + g), sigma=host(0.1 * g),
+                 Ms=host(1e4 * (1 + g)), alpha=host(0.5 * (1 + g)),
+                 gamma=host(GAMMA_E * (1 + g)), m0_dir=m0, tol=tol)
+    k = 20 * math.pi
+    e0, h0 = 1e6, 1e6 / (120 * math.pi)
+    ones = np.ones((N, N, N))
+    # (i, j, k)-indexed placements, then host layout
+    Ex = e0 * np.cos(k * xn)[None, None, :] * ones      # cos(20 pi z), z at nodes
+    Ey = e0 * np.cos(k * xn)[:, None, None] * ones      # cos(20 pi x), x at nodes
+    Ez = e0 * np.cos(k * xn)[None, :, None] * ones      # cos(20 pi y), y at nodes
+    Hx = h0 * np.cos(k * xc)[None, :, None] * ones      # cos(20 pi y), y at cell centres
+    Hy = h0 * np.cos(k * xc)[None, None, :] * ones      # cos(20 pi z), z at cell centres
+    Hz = h0 * np.cos(k * xc)[:, None, None] * ones      # cos(20 pi x), x at cell centres
+    cfg.E_init = [host(a) for a in (Ex, Ey, Ez)]
+    cfg.H_init = [host(a) for a in (Hx, Hy, Hz)]
+    return cfg
+
+
 def random_fields(cfg: Config, seed: int, amp_e: float = 1.0, amp_h: float = 1.0):
     """Seeded random E and H on every staggered entry (the solvers zero the
     PEC-wall entries themselves).  Returns (E_list, H_list) in ABI layout."""

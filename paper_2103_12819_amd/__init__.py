@@ -11,7 +11,9 @@ Coupled Electrodynamics-Micromagnetics Solver", Sec. 3.2.2.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 
 import numpy as np
 
@@ -58,8 +60,12 @@ class _TorchAlloc:
             return None
 
     def _free(self, ptr, ctx):
-        if ptr:
-            self.torch.cuda.caching_allocator_delete(int(ptr))
+        if not ptr:
+            return
+        cuda = getattr(self.torch, "cuda", None)
+        fn = getattr(cuda, "caching_allocator_delete", None)
+        if fn is not None:   # None only while the interpreter tears torch down
+            fn(int(ptr))
 
 
 class Sim:
@@ -115,6 +121,7 @@ class Sim:
                                src_p, C.byref(opt))
         if st != 0:
             raise MMError(st, "mm_init rejected the arguments")
+        _LIVE.add(self)
         self._keep = None
         self._prof = None
 
@@ -241,6 +248,16 @@ class Sim:
             self.close()
         except Exception:
             pass
+
+
+def _close_all():
+    """Close the contexts still open at exit, while torch is intact."""
+    for sim in list(_LIVE):
+        sim.close()
+
+
+_LIVE = weakref.WeakSet()
+atexit.register(_close_all)
 
 
 def from_config(cfg, precision="fp64", fixed_iter=0, with_probes=True, **kw):

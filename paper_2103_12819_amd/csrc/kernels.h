@@ -31,6 +31,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Threads per block of the magnetic-face kernels (hm_pre, hm_step,
+// hm_commit) and the cap on their blocks per CU: the grid of those launches
+// is also the number of residual partials each consumer reduces.
+#ifndef MM_MAG_THREADS
+#define MM_MAG_THREADS 256
+#endif
+#ifndef MM_MAG_BLOCKS_PER_CU
+#define MM_MAG_BLOCKS_PER_CU 4
+#endif
+
 namespace mmk {
 
 constexpr double kMu0 = 1.25663706212e-6;
@@ -158,57 +168,98 @@ __global__ __launch_bounds__(256) void e_update(Geo g, T* __restrict__ Ex, T* __
       s_im_km = sig(at(g, im, j, km));
     }
   }
+  // Software pipeline over the planes: every load of plane k+1 (H and its
+  // neighbours, the old E, the materials, the source term) is issued before
+  // plane k is computed, so one memory latency per plane overlaps the work.
+  struct Plane {
+    T hx, hy, hz, hz_jm, hx_jm, hz_im, hy_im, ex, ey, ez;
+    T e_c, e_jm, e_im, e_imjm, s_c, s_jm, s_im, s_imjm;
+    int m_c, m_jm, m_im, m_imjm;
+    double sv;
+  };
+  auto load = [&](int k, Plane& p) {
+    const int c = at(g, i, j, k), cjm = at(g, i, jm, k), cim = at(g, im, j, k), cimjm = at(g, im, jm, k);
+    p.hx = Hx[c];
+    p.hy = Hy[c];
+    p.hz = Hz[c];
+    p.hz_jm = Hz[cjm];
+    p.hx_jm = Hx[cjm];
+    p.hz_im = Hz[cim];
+    p.hy_im = Hy[cim];
+    p.ex = Ex[c];
+    p.ey = Ey[c];
+    p.ez = Ez[c];
+    if (MAT) {
+      p.m_c = mat[c];
+      p.m_jm = mat[cjm];
+      p.m_im = mat[cim];
+      p.m_imjm = mat[cimjm];
+    } else {
+      p.e_c = eps_map[c];
+      p.e_jm = eps_map[cjm];
+      p.e_im = eps_map[cim];
+      p.e_imjm = eps_map[cimjm];
+      if (SIG) {
+        p.s_c = sig_map[c];
+        p.s_jm = sig_map[cjm];
+        p.s_im = sig_map[cim];
+        p.s_imjm = sig_map[cimjm];
+      }
+    }
+    p.sv = src.comp >= 0 ? src_term(src, src.comp, i, j, k) : 0.0;
+  };
+  Plane nxt;
+  load(k0, nxt);
   for (int k = k0; k < k1; ++k) {
+    const Plane cur = nxt;
+    if (k + 1 < k1) load(k + 1, nxt);
+    __builtin_amdgcn_sched_barrier(0);
     const bool kin = pzp || k >= 1;
     const int c = at(g, i, j, k);
-    const int cjm = at(g, i, jm, k);
-    const int cim = at(g, im, j, k);
-    const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
-    const T hz_jm = Hz[cjm], hx_jm = Hx[cjm];
-    const T hz_im = Hz[cim], hy_im = Hy[cim];
-    const T e_c = eps(c), e_jm = eps(cjm), e_im = eps(cim), e_imjm = eps(at(g, im, jm, k));
+    const T e_c = MAT ? teps[cur.m_c] : cur.e_c, e_jm = MAT ? teps[cur.m_jm] : cur.e_jm;
+    const T e_im = MAT ? teps[cur.m_im] : cur.e_im, e_imjm = MAT ? teps[cur.m_imjm] : cur.e_imjm;
     T s_c = 0, s_jm = 0, s_im = 0, s_imjm = 0;
     if (SIG) {
-      s_c = sig(c);
-      s_jm = sig(cjm);
-      s_im = sig(cim);
-      s_imjm = sig(at(g, im, jm, k));
+      s_c = MAT ? tsig[cur.m_c] : cur.s_c;
+      s_jm = MAT ? tsig[cur.m_jm] : cur.s_jm;
+      s_im = MAT ? tsig[cur.m_im] : cur.s_im;
+      s_imjm = MAT ? tsig[cur.m_imjm] : cur.s_imjm;
     }
     if (jin && kin) {  // Ex at (i+1/2, j, k)
-      T curl = dq(hz - hz_jm, sdy, idy) - dq(hy - hy_km, sdz, idz);
-      if (src.comp == 0) curl = curl - (T)src_term(src, 0, i, j, k);
+      T curl = dq(cur.hz - cur.hz_jm, sdy, idy) - dq(cur.hy - hy_km, sdz, idz);
+      if (src.comp == 0) curl = curl - (T)cur.sv;
       const T ee = e0 * (quarter * ((e_jm_km + e_km) + (e_jm + e_c)));
       const T a = ee / dt;
       const T b = SIG ? (quarter * ((s_jm_km + s_km) + (s_jm + s_c))) * half : (T)0;
       const T den = a + b;
       const T ca = SIG ? (a - b) / den : (T)1;
       const T cb = (T)1 / den;
-      Ex[c] = ca * Ex[c] + cb * curl;
+      Ex[c] = ca * cur.ex + cb * curl;
     }
     if (iin && kin) {  // Ey at (i, j+1/2, k)
-      T curl = dq(hx - hx_km, sdz, idz) - dq(hz - hz_im, sdx, idx);
-      if (src.comp == 1) curl = curl - (T)src_term(src, 1, i, j, k);
+      T curl = dq(cur.hx - hx_km, sdz, idz) - dq(cur.hz - cur.hz_im, sdx, idx);
+      if (src.comp == 1) curl = curl - (T)cur.sv;
       const T ee = e0 * (quarter * ((e_im_km + e_km) + (e_im + e_c)));
       const T a = ee / dt;
       const T b = SIG ? (quarter * ((s_im_km + s_km) + (s_im + s_c))) * half : (T)0;
       const T den = a + b;
       const T ca = SIG ? (a - b) / den : (T)1;
       const T cb = (T)1 / den;
-      Ey[c] = ca * Ey[c] + cb * curl;
+      Ey[c] = ca * cur.ey + cb * curl;
     }
     if (iin && jin) {  // Ez at (i, j, k+1/2)
-      T curl = dq(hy - hy_im, sdx, idx) - dq(hx - hx_jm, sdy, idy);
-      if (src.comp == 2) curl = curl - (T)src_term(src, 2, i, j, k);
+      T curl = dq(cur.hy - cur.hy_im, sdx, idx) - dq(cur.hx - cur.hx_jm, sdy, idy);
+      if (src.comp == 2) curl = curl - (T)cur.sv;
       const T ee = e0 * (quarter * ((e_imjm + e_jm) + (e_im + e_c)));
       const T a = ee / dt;
       const T b = SIG ? (quarter * ((s_imjm + s_jm) + (s_im + s_c))) * half : (T)0;
       const T den = a + b;
       const T ca = SIG ? (a - b) / den : (T)1;
       const T cb = (T)1 / den;
-      Ez[c] = ca * Ez[c] + cb * curl;
+      Ez[c] = ca * cur.ez + cb * curl;
     }
-    hx_km = hx;
-    hy_km = hy;
+    hx_km = cur.hx;
+    hy_km = cur.hy;
     e_km = e_c;
     e_jm_km = e_jm;
     e_im_km = e_im;
@@ -251,46 +302,65 @@ __global__ __launch_bounds__(256) void h_bulk(Geo g, T* __restrict__ Hx, T* __re
   const T sdx = (T)g.dx, sdy = (T)g.dy, sdz = (T)g.dz;
   const T mu0 = (T)kMu0, half = (T)0.5;
 
+  // Software pipeline over the planes (as in e_update): plane k+1's loads
+  // are issued before plane k is computed.
+  struct Plane {
+    T ex_kp, ey_kp, ez, ez_jp, ez_ip, ey_ip, ex_jp, hx, hy, hz, mu_c, mu_im, mu_jm;
+  };
+  auto load = [&](int k, Plane& p) {
+    const int kp = up(k, g.nz, pzp);
+    const int c = at(g, i, j, k);
+    p.ex_kp = Ex[at(g, i, j, kp)];
+    p.ey_kp = Ey[at(g, i, j, kp)];
+    p.ez = Ez[c];
+    p.ez_jp = Ez[at(g, i, jp, k)];
+    p.ez_ip = Ez[at(g, ip, j, k)];
+    p.ey_ip = Ey[at(g, ip, j, k)];
+    p.ex_jp = Ex[at(g, i, jp, k)];
+    p.hx = Hx[c];
+    p.hy = Hy[c];
+    p.hz = Hz[c];
+    if (MU) {
+      p.mu_c = mu[c];
+      p.mu_im = mu[at(g, im, j, k)];
+      p.mu_jm = mu[at(g, i, jm, k)];
+    }
+  };
   T ex_k = Ex[at(g, i, j, k0)];
   T ey_k = Ey[at(g, i, j, k0)];
   T mu_km = 0;
   if (MU && (pzp || k0 >= 1)) mu_km = mu[at(g, i, j, dn(k0, g.nz, pzp))];
+  Plane nxt;
+  load(k0, nxt);
   for (int k = k0; k < k1; ++k) {
-    const int kp = up(k, g.nz, pzp);
+    const Plane cur = nxt;
+    if (k + 1 < k1) load(k + 1, nxt);
+    __builtin_amdgcn_sched_barrier(0);
     const int c = at(g, i, j, k);
-    const T ex_kp = Ex[at(g, i, j, kp)];
-    const T ey_kp = Ey[at(g, i, j, kp)];
-    const T ez = Ez[c];
-    const T ez_jp = Ez[at(g, i, jp, k)];
-    const T ez_ip = Ez[at(g, ip, j, k)];
-    const T ey_ip = Ey[at(g, ip, j, k)];
-    const T ex_jp = Ex[at(g, i, jp, k)];
-    T mu_c = 0;
-    if (MU) mu_c = mu[c];
     if (iin) {
-      const T curl = dq(ez_jp - ez, sdy, idy) - dq(ey_kp - ey_k, sdz, idz);
-      const T cf = MU ? h / (mu0 * (half * (mu[at(g, im, j, k)] + mu_c))) : coef0;
-      T v = Hx[c];
+      const T curl = dq(cur.ez_jp - cur.ez, sdy, idy) - dq(cur.ey_kp - ey_k, sdz, idz);
+      const T cf = MU ? h / (mu0 * (half * (cur.mu_im + cur.mu_c))) : coef0;
+      T v = cur.hx;
       for (int p = 0; p < NP; ++p) v = v - cf * curl;
       Hx[c] = v;
     }
     if (jin) {
-      const T curl = dq(ex_kp - ex_k, sdz, idz) - dq(ez_ip - ez, sdx, idx);
-      const T cf = MU ? h / (mu0 * (half * (mu[at(g, i, jm, k)] + mu_c))) : coef0;
-      T v = Hy[c];
+      const T curl = dq(cur.ex_kp - ex_k, sdz, idz) - dq(cur.ez_ip - cur.ez, sdx, idx);
+      const T cf = MU ? h / (mu0 * (half * (cur.mu_jm + cur.mu_c))) : coef0;
+      T v = cur.hy;
       for (int p = 0; p < NP; ++p) v = v - cf * curl;
       Hy[c] = v;
     }
     if (pzp || k >= 1) {
-      const T curl = dq(ey_ip - ey_k, sdx, idx) - dq(ex_jp - ex_k, sdy, idy);
-      const T cf = MU ? h / (mu0 * (half * (mu_km + mu_c))) : coef0;
-      T v = Hz[c];
+      const T curl = dq(cur.ey_ip - ey_k, sdx, idx) - dq(cur.ex_jp - ex_k, sdy, idy);
+      const T cf = MU ? h / (mu0 * (half * (mu_km + cur.mu_c))) : coef0;
+      T v = cur.hz;
       for (int p = 0; p < NP; ++p) v = v - cf * curl;
       Hz[c] = v;
     }
-    ex_k = ex_kp;
-    ey_k = ey_kp;
-    if (MU) mu_km = mu_c;
+    ex_k = cur.ex_kp;
+    ey_k = cur.ey_kp;
+    if (MU) mu_km = cur.mu_c;
   }
 }
 
@@ -620,7 +690,7 @@ __device__ __forceinline__ unsigned long long iterate_faces(const Geo& g, const 
 // aoms (eq:LLG_scalar, gamma_L = gamma / (1 + alpha^2)), then H from
 // eq:H_update as in iteration 1; the sub-step ends there.
 template <typename T>
-__global__ __launch_bounds__(256) void hm_pre(Geo g, Fields<T> F, Mag m, double h, double hmu0, double H0x,
+__global__ __launch_bounds__(MM_MAG_THREADS) void hm_pre(Geo g, Fields<T> F, Mag m, double h, double hmu0, double H0x,
                                              double H0y, double H0z, int first, Ctl C, int* err) {
   unsigned long long rb = 0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m.n; t += gridDim.x * blockDim.x) {
@@ -690,7 +760,7 @@ __global__ __launch_bounds__(256) void hm_pre(Geo g, Fields<T> F, Mag m, double 
 // the whole grid returns at once when it fires; block 0 then records the
 // final count.  H^{(r)} goes to H for even r and to A for odd r.
 template <typename T>
-__global__ __launch_bounds__(256) void hm_step(Geo g, Fields<T> F, Mag m, double H0x, double H0y,
+__global__ __launch_bounds__(MM_MAG_THREADS) void hm_step(Geo g, Fields<T> F, Mag m, double H0x, double H0y,
                                               double H0z, Ctl C, int r, int* err) {
   if (load_u64(&C.cur[0]) != 0ull) return;
   bool bad;
@@ -766,7 +836,7 @@ __global__ __launch_bounds__(256) void hm_finish(Geo g, Fields<T> F, Mag m, doub
 // (odd count), record the count and the sticky flags, and clear the other
 // sub-step's final count.
 template <typename T>
-__global__ __launch_bounds__(256) void hm_commit(Fields<T> F, Mag m, Ctl C, int* iters_out, int* ring,
+__global__ __launch_bounds__(MM_MAG_THREADS) void hm_commit(Fields<T> F, Mag m, Ctl C, int* iters_out, int* ring,
                                                 int* err) {
   const int rfin = (int)load_u64(&C.cur[0]);
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;

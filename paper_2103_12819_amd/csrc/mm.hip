@@ -514,7 +514,7 @@ mm_status substep(mm_ctx* c, bool near_only = false) {
   if (c->nmag > 0) {
     mmk::Mag m = make_mag(c);
     Timed tm(c, 2);
-    hipLaunchKernelGGL((mmk::hm_pre<T>), dim3(c->step_blocks), dim3(256), 0, c->stream, g, F, m, h, hmu0,
+    hipLaunchKernelGGL((mmk::hm_pre<T>), dim3(c->step_blocks), dim3(MM_MAG_THREADS), 0, c->stream, g, F, m, h, hmu0,
                        H0x, H0y, H0z, c->scheme == 1 ? 1 : 0, C, c->d_err);
   }
   HIPCHECK(c, hipGetLastError());
@@ -538,7 +538,7 @@ mm_status substep(mm_ctx* c, bool near_only = false) {
     const int R = iterations_to_enqueue(c);
     for (int r = 2; r <= R; ++r) {
       Timed tm(c, 3);
-      hipLaunchKernelGGL((mmk::hm_step<T>), dim3(c->step_blocks), dim3(256), 0, c->stream, g, F, m, H0x, H0y,
+      hipLaunchKernelGGL((mmk::hm_step<T>), dim3(c->step_blocks), dim3(MM_MAG_THREADS), 0, c->stream, g, F, m, H0x, H0y,
                          H0z, C, r, c->d_err);
     }
     HIPCHECK(c, hipGetLastError());
@@ -549,7 +549,7 @@ mm_status substep(mm_ctx* c, bool near_only = false) {
     }
     {
       Timed tm(c, 6);
-      hipLaunchKernelGGL((mmk::hm_commit<T>), dim3(c->step_blocks), dim3(256), 0, c->stream, F, m, C,
+      hipLaunchKernelGGL((mmk::hm_commit<T>), dim3(c->step_blocks), dim3(MM_MAG_THREADS), 0, c->stream, F, m, C,
                          c->d_iters + c->substep, c->d_ring + (c->substep & 63), c->d_err);
     }
     HIPCHECK(c, hipGetLastError());
@@ -1030,9 +1030,11 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
     int dev = 0, ncu = 0;
     HIPCHECK(c, hipGetDevice(&dev));
     HIPCHECK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int want = (c->nmag + 255) / 256;
-    c->step_blocks = std::max(1, std::min(want, 8 * ncu));
-    c->fin_blocks = std::max(1, std::min(want, ncu));
+    const int want = (c->nmag + MM_MAG_THREADS - 1) / MM_MAG_THREADS;
+    c->step_blocks = std::max(1, std::min(want, MM_MAG_BLOCKS_PER_CU * ncu));
+    // hm_finish: co-resident (at most one block per CU) and no more blocks
+    // than residual slots, so that every slot has an owner
+    c->fin_blocks = std::max(1, std::min(c->step_blocks, ncu));
   }
   c->d_res = (unsigned long long*)dalloc(c, 2 * sizeof(unsigned long long));
   c->d_part = (unsigned long long*)dalloc(c, 2 * (size_t)c->nres * c->step_blocks * sizeof(unsigned long long));

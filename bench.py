@@ -138,6 +138,61 @@ def run_adjoint_cost(steps=4000, ckpt=100):
             "max_abs_grad_Ms": float(np.abs(gm).max())}
 
 
+def run_scale(steps=500, ckpt=100, inner=10):
+    """The 1024x512x512 grid (268M cells) in FP32: forward `steps` steps with
+    two-level adjoint checkpoints, then the adjoint of the time-integrated
+    flux; per-kernel times of the forward, and the peak device memory."""
+    import torch
+    import paper_2103_12819_amd as mm
+
+    t0 = time.perf_counter()
+    cfg = W.scale1024(seed=0, steps=steps)
+    torch.cuda.reset_peak_memory_stats()
+    sim = mm.from_config(cfg, precision="fp32")
+    sim.enable_adjoint(ckpt, inner)
+    sim.sync()
+    setup = time.perf_counter() - t0
+    tiles = sim.tiles()
+    sim.profile(True)
+    sim.profile_read()
+    t1 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    fwd = time.perf_counter() - t1
+    kern = sim.profile_read()
+    sim.profile(False)
+    t2 = time.perf_counter()
+    ge, gm = sim.adjoint(0)
+    adj = time.perf_counter() - t2
+    _, L = sim.probe(0)
+    info = sim.info()
+    iters = sim.stats()
+    sim.close()
+    peak = torch.cuda.max_memory_allocated()
+    cells = cfg.cells
+    rl = {}
+    for k in BULK_KERNELS:
+        ms, n = kern[k]
+        if n:
+            nc = cells_per_launch(k, kern, tiles, cells, steps)
+            b = bytes_per_cell(k, 4, tiles, cfg) * nc
+            rl[k] = {"avg_launch_ms": round(ms / n, 4), "GB/s": round(b / (ms / n / 1e3) / 1e9, 1)}
+    return {"workload": f"scale1024 {cfg.n[0]}x{cfg.n[1]}x{cfg.n[2]} ({cells} cells), 3 ferrite inclusions, "
+                        f"64 dielectric boxes, FP32, {steps} steps, checkpoints every {ckpt} (inner {inner})",
+            "setup_s": round(setup, 1),
+            "forward_ms_per_step": round(fwd / steps * 1e3, 4),
+            "forward_Mcell_per_s": round(cells * steps / fwd / 1e6, 1),
+            "adjoint_s": round(adj, 2),
+            "adjoint_over_forward": round(adj / fwd, 3),
+            "kernels_ms_per_step": {k: round(v[0] / steps, 4) for k, v in kern.items()},
+            "bulk_roofline": rl,
+            "iterations_per_substep": {str(k): int(v) for k, v in zip(*np.unique(iters, return_counts=True))},
+            "peak_device_GB": round(peak / 1e9, 1),
+            "context_device_GB": round(info["device_bytes"] / 1e9, 1),
+            "loss": L, "max_abs_grad_eps_r": float(np.abs(ge).max()),
+            "max_abs_grad_Ms": float(np.abs(gm).max())}
+
+
 def cpu_baseline(budget_s=15.0):
     """The oracle on the 128x64x64 crop of the same grid, as many steps as fit
     in the time budget (at least 2)."""
@@ -172,6 +227,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--scale", action="store_true",
+                    help="also run the 1024x512x512 FP32 forward + two-level adjoint (about 2 minutes, "
+                         "~250 GB of device memory)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -256,6 +314,10 @@ def main():
         print("[bench] adjoint cost (design128)", flush=True)
         out["adjoint"] = run_adjoint_cost()
         print(f"[bench] adjoint {out['adjoint']}", flush=True)
+    if args.scale:
+        print("[bench] scale (1024x512x512 FP32, forward + adjoint)", flush=True)
+        out["scale"] = run_scale()
+        print(f"[bench] scale {out['scale']}", flush=True)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", flush=True)
         out["cpu_baseline"] = cpu_baseline()

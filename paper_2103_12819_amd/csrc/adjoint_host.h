@@ -129,13 +129,44 @@ void touched_faces(const mm_ctx* c, std::vector<int>& idx, std::vector<unsigned 
   }
 }
 
+// Largest iteration count of the sub-steps run so far (the recompute repeats
+// them exactly), at most 16: the number of iterate-log slots needed.
+mm_status iterate_slots(mm_ctx* c, int& slots) {
+  int maxit = 1;
+  if (c->nmag > 0 && c->step > 0) {
+    std::vector<int> it(2 * (size_t)c->step);
+    HIPCHECK(c, hipMemcpy(it.data(), c->d_iters, it.size() * sizeof(int), hipMemcpyDeviceToHost));
+    for (int v : it) maxit = std::max(maxit, v);
+  }
+  slots = std::min(maxit, 16);
+  return MM_OK;
+}
+
 mm_status adj_alloc(mm_ctx* c) {
-  if (c->adjw && c->adjw->K == c->ckpt_every) return MM_OK;   // enable is once, before stepping
+  int slots = 1;
+  mm_status st = iterate_slots(c, slots);
+  if (st) return st;
+  if (c->adjw) {   // allocated by an earlier call: grow the iterate logs if needed
+    AdjWork* w = c->adjw;
+    if (w->cap >= slots) {
+      c->hlog_cap = w->cap;
+      return MM_OK;
+    }
+    const size_t nm = (size_t)std::max(c->nmag, 1);
+    for (auto& lg : w->slog) {
+      dfree(c, lg);
+      lg = (double*)dalloc(c, 2 * (size_t)slots * nm * 8);
+      if (!lg) return fail(c, MM_ENOMEM, "adjoint segment storage allocation failed");
+    }
+    w->cap = slots;
+    c->hlog_cap = slots;
+    return MM_OK;
+  }
   AdjWork* w = new AdjWork();
   c->adjw = w;
   w->K = c->ckpt_every;
   w->K2 = c->ckpt_inner > 0 ? std::min(c->ckpt_inner, c->ckpt_every) : c->ckpt_every;
-  w->cap = std::min(std::max(c->max_iter, c->fixed_iter), 16);
+  w->cap = slots;
   c->hlog_cap = w->cap;
   const size_t fb = c->nelem * c->esz, fd = c->nelem * sizeof(double);
   auto need = [&](void* p) { return p != nullptr; };

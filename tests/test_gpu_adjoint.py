@@ -106,3 +106,16 @@ def test_autograd_function():
     assert np.allclose(eps.grad.numpy(), 2.0 * ge, rtol=0, atol=0)
     assert np.allclose(ms.grad.numpy(), 2.0 * gm, rtol=0, atol=0)
     assert float(np.abs(ge).max()) > 0 and float(np.abs(gm).max()) > 0
+
+
+def test_second_adjoint_call_after_more_steps():
+    """mm_adjoint, three more steps, mm_adjoint again: the second gradient
+    equals that of a fresh run of the longer horizon (the context's work
+    buffers are reused, the iterate log grown if needed)."""
+    sim, pid = _gpu(ckpt=4, inner=3)
+    sim.adjoint(pid)
+    sim.step(3)
+    g2 = sim.adjoint(pid)
+    ref, rp = _gpu(ckpt=4, inner=3, steps=OA.STEPS + 3)
+    gr = ref.adjoint(rp)
+    assert np.array_equal(g2[0], gr[0]) and np.array_equal(g2[1], gr[1])

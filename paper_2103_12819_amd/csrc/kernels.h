@@ -129,15 +129,26 @@ __global__ __launch_bounds__(256) void e_update(Geo g, T* __restrict__ Ex, T* __
                                                const T* __restrict__ eps_map, const T* __restrict__ sig_map,
                                                const unsigned char* __restrict__ mat,
                                                const T* __restrict__ mtab, T dt, Src src, Tiles tl) {
-  __shared__ T teps[MAT ? 256 : 1], tsig[MAT ? 256 : 1];
+  // Edge coefficients of an edge whose four cells share one material,
+  // per material id: the same expressions as the general path below (so
+  // equal to it bit for bit); mixed edges take the general path.
+  auto coef = [&](T e1, T e2, T e3, T e4, T s1, T s2, T s3, T s4, T& ca, T& cb) {
+    const T ee = (T)kEps0 * ((T)0.25 * ((e1 + e2) + (e3 + e4)));
+    const T a = ee / dt;
+    const T b = SIG ? ((T)0.25 * ((s1 + s2) + (s3 + s4))) * (T)0.5 : (T)0;
+    const T den = a + b;
+    ca = SIG ? (a - b) / den : (T)1;
+    cb = (T)1 / den;
+  };
+  __shared__ T teps[MAT ? 256 : 1], tsig[MAT ? 256 : 1], tca[MAT ? 256 : 1], tcb[MAT ? 256 : 1];
   if (MAT) {
     const int q = threadIdx.x + 64 * threadIdx.y;
-    teps[q] = mtab[q];
-    tsig[q] = mtab[256 + q];
+    const T e = mtab[q], sg = mtab[256 + q];
+    teps[q] = e;
+    tsig[q] = sg;
+    coef(e, e, e, e, sg, sg, sg, sg, tca[q], tcb[q]);
     __syncthreads();
   }
-  auto eps = [&](int a) -> T { return MAT ? teps[mat[a]] : eps_map[a]; };
-  auto sig = [&](int a) -> T { return MAT ? tsig[mat[a]] : sig_map[a]; };
   int i, j, k0, k1;
   tile_span(tl, g.nz, i, j, k0, k1);
   i += threadIdx.x;
@@ -150,32 +161,38 @@ __global__ __launch_bounds__(256) void e_update(Geo g, T* __restrict__ Ex, T* __
   const int jm = jin ? dn(j, g.ny, pyp) : j;
   const T idx = (T)g.idx, idy = (T)g.idy, idz = (T)g.idz;
   const T sdx = (T)g.dx, sdy = (T)g.dy, sdz = (T)g.dz;
-  const T e0 = (T)kEps0;
-  const T half = (T)0.5, quarter = (T)0.25;
-
   // plane k-1 carries
   T hx_km = 0, hy_km = 0, e_km = 0, e_jm_km = 0, e_im_km = 0, s_km = 0, s_jm_km = 0, s_im_km = 0;
+  int m_km = -1, m_jm_km = -1, m_im_km = -1;   // material ids of plane k-1 (MAT)
   if (pzp || k0 >= 1) {
     const int km = dn(k0, g.nz, pzp);
+    if (MAT) {
+      m_km = mat[at(g, i, j, km)];
+      m_jm_km = mat[at(g, i, jm, km)];
+      m_im_km = mat[at(g, im, j, km)];
+    }
     hx_km = Hx[at(g, i, j, km)];
     hy_km = Hy[at(g, i, j, km)];
-    e_km = eps(at(g, i, j, km));
-    e_jm_km = eps(at(g, i, jm, km));
-    e_im_km = eps(at(g, im, j, km));
-    if (SIG) {
-      s_km = sig(at(g, i, j, km));
-      s_jm_km = sig(at(g, i, jm, km));
-      s_im_km = sig(at(g, im, j, km));
+    if (!MAT) {
+      e_km = eps_map[at(g, i, j, km)];
+      e_jm_km = eps_map[at(g, i, jm, km)];
+      e_im_km = eps_map[at(g, im, j, km)];
+      if (SIG) {
+        s_km = sig_map[at(g, i, j, km)];
+        s_jm_km = sig_map[at(g, i, jm, km)];
+        s_im_km = sig_map[at(g, im, j, km)];
+      }
     }
   }
   // Software pipeline over the planes: every load of plane k+1 (H and its
-  // neighbours, the old E, the materials, the source term) is issued before
-  // plane k is computed, so one memory latency per plane overlaps the work.
+  // neighbours, the old E, the materials) is issued before plane k is
+  // computed, so one memory latency per plane overlaps the work.  (The
+  // source profile is read where it is used: only blocks inside its
+  // bounding box do.)
   struct Plane {
     T hx, hy, hz, hz_jm, hx_jm, hz_im, hy_im, ex, ey, ez;
     T e_c, e_jm, e_im, e_imjm, s_c, s_jm, s_im, s_imjm;
     int m_c, m_jm, m_im, m_imjm;
-    double sv;
   };
   auto load = [&](int k, Plane& p) {
     const int c = at(g, i, j, k), cjm = at(g, i, jm, k), cim = at(g, im, j, k), cimjm = at(g, im, jm, k);
@@ -206,7 +223,6 @@ __global__ __launch_bounds__(256) void e_update(Geo g, T* __restrict__ Ex, T* __
         p.s_imjm = sig_map[cimjm];
       }
     }
-    p.sv = src.comp >= 0 ? src_term(src, src.comp, i, j, k) : 0.0;
   };
   Plane nxt;
   load(k0, nxt);
@@ -216,57 +232,66 @@ __global__ __launch_bounds__(256) void e_update(Geo g, T* __restrict__ Ex, T* __
     __builtin_amdgcn_sched_barrier(0);
     const bool kin = pzp || k >= 1;
     const int c = at(g, i, j, k);
-    const T e_c = MAT ? teps[cur.m_c] : cur.e_c, e_jm = MAT ? teps[cur.m_jm] : cur.e_jm;
-    const T e_im = MAT ? teps[cur.m_im] : cur.e_im, e_imjm = MAT ? teps[cur.m_imjm] : cur.e_imjm;
-    T s_c = 0, s_jm = 0, s_im = 0, s_imjm = 0;
-    if (SIG) {
-      s_c = MAT ? tsig[cur.m_c] : cur.s_c;
-      s_jm = MAT ? tsig[cur.m_jm] : cur.s_jm;
-      s_im = MAT ? tsig[cur.m_im] : cur.s_im;
-      s_imjm = MAT ? tsig[cur.m_imjm] : cur.s_imjm;
-    }
+    // cell eps_r / sigma: from the LDS table by id (MAT; read only where an
+    // edge is mixed) or the values loaded from the maps
+    auto EV = [&](int id, T v) -> T { return MAT ? teps[id] : v; };
+    auto SV = [&](int id, T v) -> T { return SIG ? (MAT ? tsig[id] : v) : (T)0; };
+    // (the four cells of each edge, in the pairing order of the 4-cell mean)
     if (jin && kin) {  // Ex at (i+1/2, j, k)
       T curl = dq(cur.hz - cur.hz_jm, sdy, idy) - dq(cur.hy - hy_km, sdz, idz);
-      if (src.comp == 0) curl = curl - (T)cur.sv;
-      const T ee = e0 * (quarter * ((e_jm_km + e_km) + (e_jm + e_c)));
-      const T a = ee / dt;
-      const T b = SIG ? (quarter * ((s_jm_km + s_km) + (s_jm + s_c))) * half : (T)0;
-      const T den = a + b;
-      const T ca = SIG ? (a - b) / den : (T)1;
-      const T cb = (T)1 / den;
+      if (src.comp == 0) curl = curl - (T)src_term(src, 0, i, j, k);
+      T ca, cb;
+      if (MAT && m_jm_km == m_km && m_km == cur.m_jm && cur.m_jm == cur.m_c) {
+        ca = tca[cur.m_c];
+        cb = tcb[cur.m_c];
+      } else {
+        coef(EV(m_jm_km, e_jm_km), EV(m_km, e_km), EV(cur.m_jm, cur.e_jm), EV(cur.m_c, cur.e_c),
+             SV(m_jm_km, s_jm_km), SV(m_km, s_km), SV(cur.m_jm, cur.s_jm), SV(cur.m_c, cur.s_c), ca, cb);
+      }
       Ex[c] = ca * cur.ex + cb * curl;
     }
     if (iin && kin) {  // Ey at (i, j+1/2, k)
       T curl = dq(cur.hx - hx_km, sdz, idz) - dq(cur.hz - cur.hz_im, sdx, idx);
-      if (src.comp == 1) curl = curl - (T)cur.sv;
-      const T ee = e0 * (quarter * ((e_im_km + e_km) + (e_im + e_c)));
-      const T a = ee / dt;
-      const T b = SIG ? (quarter * ((s_im_km + s_km) + (s_im + s_c))) * half : (T)0;
-      const T den = a + b;
-      const T ca = SIG ? (a - b) / den : (T)1;
-      const T cb = (T)1 / den;
+      if (src.comp == 1) curl = curl - (T)src_term(src, 1, i, j, k);
+      T ca, cb;
+      if (MAT && m_im_km == m_km && m_km == cur.m_im && cur.m_im == cur.m_c) {
+        ca = tca[cur.m_c];
+        cb = tcb[cur.m_c];
+      } else {
+        coef(EV(m_im_km, e_im_km), EV(m_km, e_km), EV(cur.m_im, cur.e_im), EV(cur.m_c, cur.e_c),
+             SV(m_im_km, s_im_km), SV(m_km, s_km), SV(cur.m_im, cur.s_im), SV(cur.m_c, cur.s_c), ca, cb);
+      }
       Ey[c] = ca * cur.ey + cb * curl;
     }
     if (iin && jin) {  // Ez at (i, j, k+1/2)
       T curl = dq(cur.hy - cur.hy_im, sdx, idx) - dq(cur.hx - cur.hx_jm, sdy, idy);
-      if (src.comp == 2) curl = curl - (T)cur.sv;
-      const T ee = e0 * (quarter * ((e_imjm + e_jm) + (e_im + e_c)));
-      const T a = ee / dt;
-      const T b = SIG ? (quarter * ((s_imjm + s_jm) + (s_im + s_c))) * half : (T)0;
-      const T den = a + b;
-      const T ca = SIG ? (a - b) / den : (T)1;
-      const T cb = (T)1 / den;
+      if (src.comp == 2) curl = curl - (T)src_term(src, 2, i, j, k);
+      T ca, cb;
+      if (MAT && cur.m_imjm == cur.m_jm && cur.m_jm == cur.m_im && cur.m_im == cur.m_c) {
+        ca = tca[cur.m_c];
+        cb = tcb[cur.m_c];
+      } else {
+        coef(EV(cur.m_imjm, cur.e_imjm), EV(cur.m_jm, cur.e_jm), EV(cur.m_im, cur.e_im), EV(cur.m_c, cur.e_c),
+             SV(cur.m_imjm, cur.s_imjm), SV(cur.m_jm, cur.s_jm), SV(cur.m_im, cur.s_im), SV(cur.m_c, cur.s_c),
+             ca, cb);
+      }
       Ez[c] = ca * cur.ez + cb * curl;
     }
     hx_km = cur.hx;
     hy_km = cur.hy;
-    e_km = e_c;
-    e_jm_km = e_jm;
-    e_im_km = e_im;
-    if (SIG) {
-      s_km = s_c;
-      s_jm_km = s_jm;
-      s_im_km = s_im;
+    if (MAT) {
+      m_km = cur.m_c;
+      m_jm_km = cur.m_jm;
+      m_im_km = cur.m_im;
+    } else {
+      e_km = cur.e_c;
+      e_jm_km = cur.e_jm;
+      e_im_km = cur.e_im;
+      if (SIG) {
+        s_km = cur.s_c;
+        s_jm_km = cur.s_jm;
+        s_im_km = cur.s_im;
+      }
     }
   }
 }

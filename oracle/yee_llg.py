@@ -21,6 +21,10 @@ Coupled Electrodynamics-Micromagnetics Solver".
     iterated until the domain-wide max of |dM|/Ms drops below tol; faces
     with Ms = 0 take the plain Faraday update with mu.
   * Sec. 3.2.3: periodic and PEC boundaries.
+  * Sec. 3.2.3 (pml=...): the open boundary, a split-field perfectly
+    matched layer (Berenger) whose split parts take the macroscopic update
+    and are damped before and after it (the two-step time-centred form the
+    paper uses), with a graded damping rate matched for E and H.
   * Sec. 3.2.1 Steps 1 and 3 (scheme=1): the first-order scheme, an
     explicit step of the LLG in Landau-Lifshitz form (eq:LLG_scalar, with
     gamma_L = gamma / (1 + alpha^2)) then N(M) and eq:H_update /
@@ -161,7 +165,10 @@ class Simulation:
     per-axis periodic flags, sub-step tolerance / iteration cap, and
     `fixed_iter` (> 0: exactly that many iterations per sub-step), and
     `scheme` (2: the iterative second-order sub-step; 1: the first-order
-    scheme of Sec. 3.2.1, one explicit update per sub-step).
+    scheme of Sec. 3.2.1, one explicit update per sub-step), and `pml`:
+    None, or (cells, R0, order) with cells = (x_lo, x_hi, y_lo, y_hi, z_lo,
+    z_hi) layer thicknesses on PEC axes, the normal-incidence reflection
+    target R0 of the grading and its polynomial order.
     `dtype` complex128 runs the same arithmetic on complex numbers (all
     decisions use real parts), for complex-step derivatives in the tests.
     """
@@ -169,7 +176,8 @@ class Simulation:
     def __init__(self, n, d, dt, eps_r=None, sigma=None, mu_r=None, Ms=None,
                  alpha=None, gamma=None, m0_dir=None, H0=(0.0, 0.0, 0.0),
                  source=None, periodic=(False, False, False), tol=1e-10,
-                 max_iter=100, fixed_iter=0, raise_on_noconv=False, dtype=np.float64, scheme=2):
+                 max_iter=100, fixed_iter=0, raise_on_noconv=False, dtype=np.float64, scheme=2,
+                 pml=None):
         self.dtype = np.dtype(dtype)
         assert scheme in (1, 2)
         self.scheme = int(scheme)
@@ -204,6 +212,7 @@ class Simulation:
             m0 = [to_ijk(np.asarray(m0_dir)[c]) for c in range(3)]
         self.m0_dir = m0
         self._prepare(m0)
+        self._prepare_pml(pml)
 
         # fields on the Yee grid (Sec. 3.1)
         self.E = [np.zeros(self.edge_shape(c), dtype=self.dtype) for c in range(3)]
@@ -364,6 +373,98 @@ class Simulation:
             out.append(hc + self.H0[c])
         return out
 
+    # ---- open boundary: split-field PML (Sec. 3.2.3) ------------------------
+    # Component c of E (or H) splits into the part driven by the positive
+    # term of its curl, P (derivative along axis p), and the rest (axis m):
+    #   E: x: p = y, m = z;  y: p = z, m = x;  z: p = x, m = y  (same for H).
+    # P is stored; the full field stays in E / H.  In the layer each part takes
+    # the macroscopic update and is multiplied by exp(-kappa dt/2) before and
+    # after it (E, a full step) or by exp(-kappa dt/4) (H, each half step),
+    # kappa(depth) = kappa_max (depth / L)^order along the part's axis,
+    # kappa_max = -(order + 1) c ln(R0) / (2 L).  kappa is a rate (sigma/eps
+    # for E, sigma*/mu for H), so the layer is matched in any non-magnetic
+    # material.  Entries with kappa = 0 for both parts take the plain update.
+    PM = ((1, 2), (2, 0), (0, 1))
+
+    def _prepare_pml(self, pml):
+        self.pml = None
+        if pml is None:
+            return
+        cells, R0, order = pml
+        cells = tuple(int(v) for v in cells)
+        if not any(cells):
+            return
+        c0 = 299792458.0
+        node_k, cent_k = [], []
+        for a in range(3):
+            lo, hi = cells[2 * a], cells[2 * a + 1]
+            n = self.n[a]
+            if (lo or hi) and self.per[a]:
+                raise ValueError("a PML needs a PEC (non-periodic) axis")
+            xn = np.arange(n + 1, dtype=np.float64)     # node positions (cells)
+            xc = np.arange(n, dtype=np.float64) + 0.5    # cell-centre positions
+            kn, kc = np.zeros(n + 1), np.zeros(n)
+            for thick, depth_n, depth_c in ((lo, lo - xn, lo - xc), (hi, xn - (n - hi), xc - (n - hi))):
+                if thick <= 0:
+                    continue
+                L = thick * self.d[a]
+                kmax = -(order + 1) * c0 * math.log(R0) / (2.0 * L)
+                kn = kn + np.where(depth_n > 0, kmax * (np.clip(depth_n, 0, None) / thick) ** order, 0.0)
+                kc = kc + np.where(depth_c > 0, kmax * (np.clip(depth_c, 0, None) / thick) ** order, 0.0)
+            node_k.append(kn if not self.per[a] else kn[:n])
+            cent_k.append(kc)
+        dt = self.dt
+
+        def bcast(v, ax):
+            return v.reshape([-1 if b == ax else 1 for b in range(3)])
+        # E_c lives on nodes along its transverse axes; H_f on cell centres
+        self.pml = {"dE": [], "dH": [], "onE": [], "onH": [], "PE": [], "PH": []}
+        for c in range(3):
+            p, m = self.PM[c]
+            kp = np.broadcast_to(bcast(node_k[p], p), self.edge_shape(c))
+            km = np.broadcast_to(bcast(node_k[m], m), self.edge_shape(c))
+            self.pml["dE"].append((np.exp(-kp * dt / 2.0), np.exp(-km * dt / 2.0)))
+            self.pml["onE"].append((kp > 0) | (km > 0))
+            self.pml["PE"].append(np.zeros(self.edge_shape(c), dtype=self.dtype))
+            kp = np.broadcast_to(bcast(cent_k[p], p), self.face_shape(c))
+            km = np.broadcast_to(bcast(cent_k[m], m), self.face_shape(c))
+            self.pml["dH"].append((np.exp(-kp * dt / 4.0), np.exp(-km * dt / 4.0)))
+            on = (kp > 0) | (km > 0)
+            self.pml["onH"].append(on)
+            self.pml["PH"].append(np.zeros(self.face_shape(c), dtype=self.dtype))
+            if np.any(on & self.mag[c]):
+                raise ValueError("magnetic faces inside the PML are not supported (Sec. 3.2.3)")
+
+    def _curl_terms_H(self, H, c):
+        """The two terms of (curl H)_c at the edges: T_p - T_m."""
+        p, m = self.PM[c]
+        return (d_down(H[3 - c - p], p, self.per[p]) / self.d[p],
+                d_down(H[3 - c - m], m, self.per[m]) / self.d[m])
+
+    def _curl_terms_E(self, E, f):
+        """The two terms of (curl E)_f at the faces: T_p - T_m."""
+        p, m = self.PM[f]
+        return (d_up(E[3 - f - p], p, self.per[p]) / self.d[p],
+                d_up(E[3 - f - m], m, self.per[m]) / self.d[m])
+
+    def _pml_h(self, Hs, Hplain, f, h, E):
+        """H of family f after a half step with the layer: the plain update
+        outside it, the split update inside."""
+        if self.pml is None:
+            return Hplain
+        on = self.pml["onH"][f] & self.h_interior[f]
+        if not on.any():
+            return Hplain
+        dp, dm = self.pml["dH"][f]
+        Tp, Tm = self._curl_terms_E(E, f)
+        P = self.pml["PH"][f]
+        Mpart = Hs[f] - P
+        cf = h / self.mu_f[f]
+        Pn = dp * (dp * P - cf * Tp)
+        Mn = dm * (dm * Mpart + cf * Tm)
+        self.pml["PH"][f] = np.where(on, Pn, P)
+        return np.where(on, Pn + Mn, Hplain)
+
     # ---- Step 1 / Step 3 of the first-order scheme (Sec. 3.2.1) -----------
     def hm_substep_first_order(self, C):
         """M^{new} = N(M + (dt/2) [mu0 gamma_L M x H_eff + (alpha mu0 gamma_L / Ms)
@@ -388,6 +489,7 @@ class Simulation:
             Mn = [np.where(ev, Mn[c], M[c]) for c in range(3)]
             q = Hs[f] + M[f] - (h / MU0) * C[f]
             H_nonmag = np.where(self.h_interior[f], Hs[f] - (h / self.mu_f[f]) * C[f], Hs[f])
+            H_nonmag = self._pml_h(Hs, H_nonmag, f, h, self._E_for_C)
             Hn_all.append(np.where(ev, q - Mn[f], H_nonmag))
             Mn_all.append(Mn)
         self.H = Hn_all
@@ -408,7 +510,8 @@ class Simulation:
         H_nonmag, q, b, dvec, kappa = [], [], [], [], []
         for f in range(3):
             # faces with Ms = 0: Faraday with the local mu (eq:Faraday3)
-            H_nonmag.append(np.where(self.h_interior[f], Hs[f] - (h / self.mu_f[f]) * C[f], Hs[f]))
+            H_nonmag.append(self._pml_h(Hs, np.where(self.h_interior[f], Hs[f] - (h / self.mu_f[f]) * C[f], Hs[f]),
+                                        f, h, self._E_for_C))
             # iteration-invariant parts of eq:llg_tra5/6 and eq:iterate_H
             kap = MU0 * self.gamma_f[f] * self.dt / 4.0
             He = self.H_eff(Hs, f)
@@ -473,9 +576,23 @@ class Simulation:
         for c in range(3):
             rhs = CH[c]
             if self.src is not None and self.src[0] == c:
-                comp, prof, f0, Tp, t0 = self.src
-                rhs = rhs - prof * waveform(t_half, f0, Tp, t0)
-            self.E[c] = np.where(self.e_interior[c], self.ca[c] * self.E[c] + self.cb[c] * rhs, 0.0)
+                comp, prof, f0, Tp_, t0 = self.src
+                rhs = rhs - prof * waveform(t_half, f0, Tp_, t0)
+            Eplain = np.where(self.e_interior[c], self.ca[c] * self.E[c] + self.cb[c] * rhs, 0.0)
+            if self.pml is not None and self.pml["onE"][c].any():
+                on = self.pml["onE"][c] & self.e_interior[c]
+                dp, dm = self.pml["dE"][c]
+                Tp, Tm = self._curl_terms_H(self.H, c)
+                rp = Tp
+                if self.src is not None and self.src[0] == c:
+                    rp = Tp - prof * waveform(t_half, f0, Tp_, t0)
+                P = self.pml["PE"][c]
+                Mpart = self.E[c] - P
+                Pn = dp * (self.ca[c] * (dp * P) + self.cb[c] * rp)
+                Mn = dm * (self.ca[c] * (dm * Mpart) - self.cb[c] * Tm)
+                self.pml["PE"][c] = np.where(on, Pn, P)
+                Eplain = np.where(on, Pn + Mn, Eplain)
+            self.E[c] = Eplain
 
     # ---- one full step n -> n+1 --------------------------------------------
     def step(self, nsteps=1, tape=None):
@@ -485,8 +602,10 @@ class Simulation:
             rec = None
             if tape is not None:
                 rec = {"n": self.step_count, "E0": [a.copy() for a in self.E], "tr1": {}, "tr3": {}}
+            self._E_for_C = self.E
             self.hm_substep(self.curl_E(self.E), trace=None if rec is None else rec["tr1"])  # Step 1
             self.e_update()                                                                  # Step 2
+            self._E_for_C = self.E
             self.hm_substep(self.curl_E(self.E), trace=None if rec is None else rec["tr3"])  # Step 3
             self.step_count += 1
             if rec is not None:

@@ -224,6 +224,7 @@ class Simulation:
             assert prof.shape == self.edge_shape(comp)
             self.src = (int(comp), prof * self.e_interior[comp], float(f0), float(Tp), float(t0))
         self.step_count = 0
+        self._E_for_C = None     # the E whose curl the current sub-step uses (for the PML split)
         self.iters = []          # iterations used by every sub-step, in order
         self.noconv = False
         self.nonfinite = False
@@ -452,6 +453,7 @@ class Simulation:
         outside it, the split update inside."""
         if self.pml is None:
             return Hplain
+        assert E is not None, "with a PML, sub-steps run through step()"
         on = self.pml["onH"][f] & self.h_interior[f]
         if not on.any():
             return Hplain

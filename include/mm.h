@@ -88,6 +88,23 @@ typedef struct {
   double f0, Tp, t0;
 } mm_source;
 
+/* Open boundary (Sec. 3.2.3): a split-field perfectly matched layer.
+ * cells[2a], cells[2a+1]: thickness in cells of the layer at the low / high
+ * end of axis a (a PEC axis; 0: none; the wall behind it stays PEC).  Each
+ * E and H component is split into the parts driven by the two terms of its
+ * curl; in the layer each part takes the macroscopic update and is damped
+ * by exp(-kappa dt/2) (E) or exp(-kappa dt/4) (each H half step) before and
+ * after it, kappa = kappa_max (depth / thickness)^order along the part's
+ * axis, kappa_max = -(order + 1) c ln(R0) / (2 thickness).  kappa is a rate
+ * shared by E and H, so the layer is matched in any non-conducting,
+ * non-magnetic material.  Magnetic faces inside a layer and the adjoint
+ * with a layer are not supported (MM_EINVAL). */
+typedef struct {
+  int32_t cells[6];
+  double R0;              /* 0 < R0 < 1 */
+  double order;           /* >= 1 */
+} mm_pml;
+
 /* Options.  dev_alloc/dev_free, when both are set, supply all device memory
  * of the context (e.g. a caching allocator); otherwise hipMalloc/hipFree. */
 typedef struct {
@@ -105,6 +122,7 @@ typedef struct {
                              (Sec. 3.2.2); 1: the first-order scheme of Sec. 3.2.1
                              (one explicit Landau-Lifshitz step of M per half step,
                              then eq:H_update; tol, max_iter and fixed_iter unused) */
+  const mm_pml *pml;      /* NULL: no open boundary */
 } mm_options;
 
 typedef struct mm_ctx mm_ctx;
@@ -175,9 +193,11 @@ mm_status mm_info(const mm_ctx *c, int64_t out[8]);
  * 1 of the next, in one fused pass), cells in near tiles, cells in far
  * tiles, planes per tile, the number of distinct (eps_r, sigma) pairs when
  * the E update reads byte material ids instead of the two cell maps (at
- * most 256; 0: dense maps), 0.  The far tiles' lag is invisible at the
- * interface: probes read the level they sample, and every call ends with
- * all tiles at level n. */
+ * most 256; 0: dense maps), tiles holding open-boundary layer entries
+ * (updated by the layer kernels in every half step; "bulk tiles" above
+ * count the others).  The far tiles' lag is invisible at the interface:
+ * probes read the level they sample, and every call ends with all tiles at
+ * level n. */
 mm_status mm_layout(const mm_ctx *c, int64_t out[8]);
 
 /* Adjoint (an addition to the paper's method).  mm_adjoint_enable, called

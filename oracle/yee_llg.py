@@ -671,7 +671,8 @@ def from_config(cfg, fixed_iter=0, with_probes=True, **kw):
     sim = Simulation(cfg.n, cfg.d, cfg.dt, eps_r=cfg.eps_r, sigma=cfg.sigma,
                      mu_r=cfg.mu_r, Ms=cfg.Ms, alpha=cfg.alpha, gamma=cfg.gamma,
                      m0_dir=cfg.m0_dir, H0=cfg.H0, source=src, periodic=cfg.periodic,
-                     tol=cfg.tol, max_iter=cfg.max_iter, fixed_iter=fixed_iter, **kw)
+                     tol=cfg.tol, max_iter=cfg.max_iter, fixed_iter=fixed_iter,
+                     **({"pml": cfg.pml} if cfg.pml is not None else {}), **kw)
     if cfg.E_init is not None or cfg.H_init is not None:
         sim.set_fields(cfg.E_init, cfg.H_init)
     if with_probes:

@@ -74,15 +74,17 @@ class Sim:
     Arguments follow mm_init: grid cells `n`, spacings `d`, time step `dt`,
     cell maps in host layout (x fastest: numpy shape (nz, ny, nx)), bias
     `H0`, optional source (comp, profile, f0, Tp, t0), periodic flags,
-    precision 'fp64' or 'fp32', tol, max_iter, fixed_iter, and `scheme` 2
-    (second-order, iterative) or 1 (first-order).  `stream` is a raw
-    hipStream_t (int) or None for torch's current stream.
+    precision 'fp64' or 'fp32', tol, max_iter, fixed_iter, `scheme` 2
+    (second-order, iterative) or 1 (first-order), and `pml`: None or
+    (cells, R0, order), cells = layer thicknesses (x_lo, x_hi, y_lo, y_hi,
+    z_lo, z_hi) (see mm_pml).  `stream` is a raw hipStream_t (int) or None
+    for torch's current stream.
     """
 
     def __init__(self, n, d, dt, eps_r=None, sigma=None, mu_r=None, Ms=None, alpha=None,
                  gamma=None, m0_dir=None, H0=(0.0, 0.0, 0.0), source=None,
                  periodic=(False, False, False), precision="fp64", tol=1e-10, max_iter=100,
-                 fixed_iter=0, stream=None, torch_alloc=True, scheme=2):
+                 fixed_iter=0, stream=None, torch_alloc=True, scheme=2, pml=None):
         self._lib = N.load()
         self._ctx = C.c_void_p()
         g = N.mm_grid(int(n[0]), int(n[1]), int(n[2]),
@@ -110,6 +112,10 @@ class Sim:
         opt.max_iter = int(max_iter)
         opt.fixed_iter = int(fixed_iter)
         opt.scheme = int(scheme)
+        if pml is not None:
+            cells, R0, order = pml
+            self._pml = N.mm_pml((C.c_int32 * 6)(*[int(v) for v in cells]), float(R0), float(order))
+            opt.pml = C.pointer(self._pml)
         opt.hip_stream = self.stream or None
         self._alloc = None
         if torch_alloc:
@@ -207,8 +213,8 @@ class Sim:
         out = (C.c_int64 * 8)()
         self._check(self._lib.mm_layout(self._ctx, out))
         keys = ["tiles", "near_tiles", "far_tiles", "near_cells", "far_cells", "planes_per_tile",
-                "materials"]
-        return dict(zip(keys, list(out)[:7]))
+                "materials", "pml_tiles"]
+        return dict(zip(keys, list(out)))
 
     def enable_adjoint(self, checkpoint_every=100, inner_every=0):
         """Save checkpoints while stepping so that adjoint() can run (before the
@@ -269,7 +275,7 @@ def from_config(cfg, precision="fp64", fixed_iter=0, with_probes=True, **kw):
     sim = Sim(cfg.n, cfg.d, cfg.dt, eps_r=cfg.eps_r, sigma=cfg.sigma, mu_r=cfg.mu_r, Ms=cfg.Ms,
               alpha=cfg.alpha, gamma=cfg.gamma, m0_dir=cfg.m0_dir, H0=cfg.H0, source=src,
               periodic=cfg.periodic, precision=precision, tol=cfg.tol, max_iter=cfg.max_iter,
-              fixed_iter=fixed_iter, **kw)
+              fixed_iter=fixed_iter, **({"pml": cfg.pml} if cfg.pml is not None else {}), **kw)
     if cfg.E_init is not None or cfg.H_init is not None:
         sim.set_fields(cfg.E_init, cfg.H_init)
     if with_probes:

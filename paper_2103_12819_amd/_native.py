@@ -41,11 +41,15 @@ class mm_source(C.Structure):
                 ("Tp", C.c_double), ("t0", C.c_double)]
 
 
+class mm_pml(C.Structure):
+    _fields_ = [("cells", C.c_int32 * 6), ("R0", C.c_double), ("order", C.c_double)]
+
+
 class mm_options(C.Structure):
     _fields_ = [("prec", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("fixed_iter", C.c_int32), ("hip_stream", C.c_void_p),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p),
-                ("scheme", C.c_int32)]
+                ("scheme", C.c_int32), ("pml", C.POINTER(mm_pml))]
 
 
 class mm_probe_desc(C.Structure):

@@ -390,6 +390,151 @@ __global__ __launch_bounds__(256) void h_bulk(Geo g, T* __restrict__ Hx, T* __re
 }
 
 // ---------------------------------------------------------------------------
+// Open boundary (Sec. 3.2.3): split-field perfectly matched layer on the
+// tiles that hold layer entries.  Component c splits into the part driven by
+// the positive term of its curl, P (derivative along axis p), and the rest
+// (axis m): x: p = y, m = z;  y: p = z, m = x;  z: p = x, m = y.  The full
+// field stays in E / H and P in a side array.  In the layer (damping rate
+// kappa > 0 along p or m at the entry) each part takes the macroscopic
+// update and is multiplied by the damping factor of its axis before and
+// after it: exp(-kappa dt/2) for E, exp(-kappa dt/4) for each H half step.
+// Other entries take the plain update of e_update / h_bulk (the same
+// arithmetic, so the same bits).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Pml {
+  const double* dn[3];          // E factor at the nodes of axis a
+  const double* dc[3];          // H factor at the cell centres of axis a
+  const unsigned char* on_n[3];  // kappa > 0 at the nodes of axis a
+  const unsigned char* on_c[3];  // kappa > 0 at the cell centres of axis a
+  T* PE[3];
+  T* PH[3];
+};
+
+template <typename T, bool SIG>
+__global__ __launch_bounds__(256) void pml_e(Geo g, T* __restrict__ Ex, T* __restrict__ Ey, T* __restrict__ Ez,
+                                            const T* __restrict__ Hx, const T* __restrict__ Hy,
+                                            const T* __restrict__ Hz, const T* __restrict__ eps,
+                                            const T* __restrict__ sig, T dt, Src src, Tiles tl, Pml<T> P) {
+  int i, j, k0, k1;
+  tile_span(tl, g.nz, i, j, k0, k1);
+  i += threadIdx.x;
+  j += threadIdx.y;
+  if (i >= g.nx || j >= g.ny || k0 >= k1) return;
+  const bool pxp = g.per & 1, pyp = g.per & 2, pzp = g.per & 4;
+  const bool iin = pxp || i >= 1, jin = pyp || j >= 1;
+  const int im = iin ? dn(i, g.nx, pxp) : i;
+  const int jm = jin ? dn(j, g.ny, pyp) : j;
+  const T idx = (T)g.idx, idy = (T)g.idy, idz = (T)g.idz;
+  const T sdx = (T)g.dx, sdy = (T)g.dy, sdz = (T)g.dz;
+  auto coef = [&](T e1, T e2, T e3, T e4, T s1, T s2, T s3, T s4, T& ca, T& cb) {
+    const T ee = (T)kEps0 * ((T)0.25 * ((e1 + e2) + (e3 + e4)));
+    const T a = ee / dt;
+    const T b = SIG ? ((T)0.25 * ((s1 + s2) + (s3 + s4))) * (T)0.5 : (T)0;
+    const T den = a + b;
+    ca = SIG ? (a - b) / den : (T)1;
+    cb = (T)1 / den;
+  };
+  auto S = [&](int a) -> T { return SIG ? sig[a] : (T)0; };
+  // one component: plain update, or the split update in the layer
+  auto upd = [&](T* E, T* PE, int c, T tp, T tm, T sv, T ca, T cb, double dpv, double dmv, bool on) {
+    if (!on) {
+      T curl = tp - tm;
+      curl = curl - sv;
+      E[c] = ca * E[c] + cb * curl;
+    } else {
+      const T dp = (T)dpv, dm = (T)dmv;
+      const T pv = PE[c], mv = E[c] - pv;
+      const T pn = dp * (ca * (dp * pv) + cb * (tp - sv));
+      const T mn = dm * (ca * (dm * mv) - cb * tm);
+      PE[c] = pn;
+      E[c] = pn + mn;
+    }
+  };
+  for (int k = k0; k < k1; ++k) {
+    const bool kin = pzp || k >= 1;
+    const int km = kin ? dn(k, g.nz, pzp) : k;
+    const int c = at(g, i, j, k), cjm = at(g, i, jm, k), cim = at(g, im, j, k), ckm = at(g, i, j, km);
+    if (jin && kin) {  // Ex: p = y (node j), m = z (node k)
+      const T tp = dq(Hz[c] - Hz[cjm], sdy, idy), tm = dq(Hy[c] - Hy[ckm], sdz, idz);
+      const T sv = src.comp == 0 ? (T)src_term(src, 0, i, j, k) : (T)0;
+      T ca, cb;
+      coef(eps[at(g, i, jm, km)], eps[ckm], eps[cjm], eps[c], S(at(g, i, jm, km)), S(ckm), S(cjm), S(c), ca, cb);
+      upd(Ex, P.PE[0], c, tp, tm, sv, ca, cb, P.dn[1][j], P.dn[2][k], P.on_n[1][j] || P.on_n[2][k]);
+    }
+    if (iin && kin) {  // Ey: p = z (node k), m = x (node i)
+      const T tp = dq(Hx[c] - Hx[ckm], sdz, idz), tm = dq(Hz[c] - Hz[cim], sdx, idx);
+      const T sv = src.comp == 1 ? (T)src_term(src, 1, i, j, k) : (T)0;
+      T ca, cb;
+      coef(eps[at(g, im, j, km)], eps[ckm], eps[cim], eps[c], S(at(g, im, j, km)), S(ckm), S(cim), S(c), ca, cb);
+      upd(Ey, P.PE[1], c, tp, tm, sv, ca, cb, P.dn[2][k], P.dn[0][i], P.on_n[2][k] || P.on_n[0][i]);
+    }
+    if (iin && jin) {  // Ez: p = x (node i), m = y (node j)
+      const T tp = dq(Hy[c] - Hy[cim], sdx, idx), tm = dq(Hx[c] - Hx[cjm], sdy, idy);
+      const T sv = src.comp == 2 ? (T)src_term(src, 2, i, j, k) : (T)0;
+      T ca, cb;
+      coef(eps[at(g, im, jm, k)], eps[cjm], eps[cim], eps[c], S(at(g, im, jm, k)), S(cjm), S(cim), S(c), ca, cb);
+      upd(Ez, P.PE[2], c, tp, tm, sv, ca, cb, P.dn[0][i], P.dn[1][j], P.on_n[0][i] || P.on_n[1][j]);
+    }
+  }
+}
+
+// One H half step on the layer tiles (every face, like h_bulk with NP = 1;
+// magnetic faces there are overwritten by the iteration afterwards).
+template <typename T, bool MU>
+__global__ __launch_bounds__(256) void pml_h(Geo g, T* __restrict__ Hx, T* __restrict__ Hy, T* __restrict__ Hz,
+                                            const T* __restrict__ Ex, const T* __restrict__ Ey,
+                                            const T* __restrict__ Ez, const T* __restrict__ mu, T coef0, T h,
+                                            Tiles tl, Pml<T> P) {
+  int i, j, k0, k1;
+  tile_span(tl, g.nz, i, j, k0, k1);
+  i += threadIdx.x;
+  j += threadIdx.y;
+  if (i >= g.nx || j >= g.ny || k0 >= k1) return;
+  const bool pxp = g.per & 1, pyp = g.per & 2, pzp = g.per & 4;
+  const bool iin = pxp || i >= 1, jin = pyp || j >= 1;
+  const int ip = up(i, g.nx, pxp), jp = up(j, g.ny, pyp);
+  const int im = iin ? dn(i, g.nx, pxp) : i;
+  const int jm = jin ? dn(j, g.ny, pyp) : j;
+  const T idx = (T)g.idx, idy = (T)g.idy, idz = (T)g.idz;
+  const T sdx = (T)g.dx, sdy = (T)g.dy, sdz = (T)g.dz;
+  const T mu0 = (T)kMu0, half = (T)0.5;
+  auto upd = [&](T* H, T* PH, int c, T tp, T tm, T cf, double dpv, double dmv, bool on) {
+    if (!on) {
+      const T curl = tp - tm;
+      H[c] = H[c] - cf * curl;
+    } else {
+      const T dp = (T)dpv, dm = (T)dmv;
+      const T pv = PH[c], mv = H[c] - pv;
+      const T pn = dp * (dp * pv - cf * tp);
+      const T mn = dm * (dm * mv + cf * tm);
+      PH[c] = pn;
+      H[c] = pn + mn;
+    }
+  };
+  for (int k = k0; k < k1; ++k) {
+    const int kp = up(k, g.nz, pzp);
+    const int c = at(g, i, j, k);
+    if (iin) {  // Hx: p = y (centre j), m = z (centre k)
+      const T tp = dq(Ez[at(g, i, jp, k)] - Ez[c], sdy, idy), tm = dq(Ey[at(g, i, j, kp)] - Ey[c], sdz, idz);
+      const T cf = MU ? h / (mu0 * (half * (mu[at(g, im, j, k)] + mu[c]))) : coef0;
+      upd(Hx, P.PH[0], c, tp, tm, cf, P.dc[1][j], P.dc[2][k], P.on_c[1][j] || P.on_c[2][k]);
+    }
+    if (jin) {  // Hy: p = z (centre k), m = x (centre i)
+      const T tp = dq(Ex[at(g, i, j, kp)] - Ex[c], sdz, idz), tm = dq(Ez[at(g, ip, j, k)] - Ez[c], sdx, idx);
+      const T cf = MU ? h / (mu0 * (half * (mu[at(g, i, jm, k)] + mu[c]))) : coef0;
+      upd(Hy, P.PH[1], c, tp, tm, cf, P.dc[2][k], P.dc[0][i], P.on_c[2][k] || P.on_c[0][i]);
+    }
+    if (pzp || k >= 1) {  // Hz: p = x (centre i), m = y (centre j)
+      const int km = dn(k, g.nz, pzp);
+      const T tp = dq(Ey[at(g, ip, j, k)] - Ey[c], sdx, idx), tm = dq(Ex[at(g, i, jp, k)] - Ex[c], sdy, idy);
+      const T cf = MU ? h / (mu0 * (half * (mu[at(g, i, j, km)] + mu[c]))) : coef0;
+      upd(Hz, P.PH[2], c, tp, tm, cf, P.dc[0][i], P.dc[1][j], P.on_c[0][i] || P.on_c[1][j]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Magnetic faces (compact list; families 0, 1, 2 stored contiguously).
 // ---------------------------------------------------------------------------
 template <typename T>

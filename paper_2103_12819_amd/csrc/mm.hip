@@ -145,6 +145,19 @@ struct mm_ctx {
   int n_all, n_near, n_far;
   unsigned char* d_far;      // per tile id: 1 if far
   long long cells_near, cells_far;
+  int* d_tl_pml;             // tiles holding open-boundary layer entries
+  int n_pml;
+
+  // open boundary (split-field PML): per axis damping factors at nodes (E)
+  // and cell centres (H), kappa > 0 flags, the stored split parts
+  bool has_pml;
+  int pml_cells[6];
+  double pml_R0, pml_order;
+  std::vector<double> pml_kn[3], pml_kc[3];   // kappa at nodes / centres (host)
+  double *d_pdn[3], *d_pdc[3];
+  unsigned char *d_pon_n[3], *d_pon_c[3];
+  void* PE[3];
+  void* PH[3];
 
   // optional kernel timing (mm_profile)
   bool prof;
@@ -464,6 +477,20 @@ mmk::Tiles tiles(const mm_ctx* c, const int* list, int split = 1) {
   return t;
 }
 
+template <typename T>
+mmk::Pml<T> make_pml(const mm_ctx* c) {
+  mmk::Pml<T> P;
+  for (int a = 0; a < 3; ++a) {
+    P.dn[a] = c->d_pdn[a];
+    P.dc[a] = c->d_pdc[a];
+    P.on_n[a] = c->d_pon_n[a];
+    P.on_c[a] = c->d_pon_c[a];
+    P.PE[a] = (T*)c->PE[a];
+    P.PH[a] = (T*)c->PH[a];
+  }
+  return P;
+}
+
 // z-split for a launch over n tiles: enough blocks to fill the chip
 // (~2048), runs of at least 4 planes.
 int split_for(const mm_ctx* c, int n) {
@@ -532,6 +559,20 @@ mm_status substep(mm_ctx* c, bool near_only = false) {
                          (T*)c->H[1], (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2],
                          (const T*)c->mu, (T)hmu0, (T)h, tl);
   }
+  if (c->n_pml > 0) {
+    const int split = split_for(c, c->n_pml);
+    const mmk::Tiles tl = tiles(c, c->d_tl_pml, split);
+    const mmk::Pml<T> P = make_pml<T>(c);
+    Timed tm(c, 1);
+    if (c->mu)
+      hipLaunchKernelGGL((mmk::pml_h<T, true>), dim3(c->n_pml * split), dim3(64, 4), 0, c->stream, g,
+                         (T*)c->H[0], (T*)c->H[1], (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1],
+                         (const T*)c->E[2], (const T*)c->mu, (T)hmu0, (T)h, tl, P);
+    else
+      hipLaunchKernelGGL((mmk::pml_h<T, false>), dim3(c->n_pml * split), dim3(64, 4), 0, c->stream, g,
+                         (T*)c->H[0], (T*)c->H[1], (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1],
+                         (const T*)c->E[2], (const T*)c->mu, (T)hmu0, (T)h, tl, P);
+  }
   HIPCHECK(c, hipGetLastError());
   if (c->nmag > 0) {
     mmk::Mag m = make_mag(c);
@@ -585,7 +626,8 @@ mm_status e_step(mm_ctx* c) {
   hipLaunchKernelGGL((mmk::e_update<T, SIG, MAT>), dim3(c->n_all), dim3(64, 4), 0, c->stream, g, (T*)c->E[0], \
                      (T*)c->E[1], (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2],       \
                      (const T*)c->eps, (const T*)c->sig, c->mat, (const T*)c->mtab, (T)c->dt, src, tl)
-  if (c->mat) {
+  if (c->n_all == 0) {
+  } else if (c->mat) {
     if (c->sig) MM_EUPD(true, true);
     else MM_EUPD(false, true);
   } else {
@@ -593,6 +635,19 @@ mm_status e_step(mm_ctx* c) {
     else MM_EUPD(false, false);
   }
 #undef MM_EUPD
+  if (c->n_pml > 0) {
+    const int split = split_for(c, c->n_pml);
+    const mmk::Tiles tp = tiles(c, c->d_tl_pml, split);
+    const mmk::Pml<T> P = make_pml<T>(c);
+    if (c->sig)
+      hipLaunchKernelGGL((mmk::pml_e<T, true>), dim3(c->n_pml * split), dim3(64, 4), 0, c->stream, g,
+                         (T*)c->E[0], (T*)c->E[1], (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1],
+                         (const T*)c->H[2], (const T*)c->eps, (const T*)c->sig, (T)c->dt, src, tp, P);
+    else
+      hipLaunchKernelGGL((mmk::pml_e<T, false>), dim3(c->n_pml * split), dim3(64, 4), 0, c->stream, g,
+                         (T*)c->E[0], (T*)c->E[1], (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1],
+                         (const T*)c->H[2], (const T*)c->eps, (const T*)c->sig, (T)c->dt, src, tp, P);
+  }
   HIPCHECK(c, hipGetLastError());
   return MM_OK;
 }
@@ -720,6 +775,96 @@ bool finite_nonneg(const double* a, size_t n, bool strictly_positive) {
   return true;
 }
 
+// Open boundary: damping rate kappa per axis at the nodes and the cell
+// centres, kappa = kappa_max (depth / thickness)^order inside a layer
+// (depth in cells from its inner face), kappa_max = -(order + 1) c ln(R0) /
+// (2 thickness); both layers of an axis add.
+mm_status setup_pml(mm_ctx* c, const mm_pml* p) {
+  c->has_pml = false;
+  for (int a = 0; a < 6; ++a) c->pml_cells[a] = 0;
+  if (!p) return MM_OK;
+  const int n3[3] = {c->nx, c->ny, c->nz};
+  const double d3[3] = {c->dx, c->dy, c->dz};
+  for (int a = 0; a < 3; ++a) {
+    const int lo = p->cells[2 * a], hi = p->cells[2 * a + 1];
+    if (lo < 0 || hi < 0 || lo + hi >= n3[a]) return fail(c, MM_EINVAL, "bad PML thickness on axis %d", a);
+    if ((lo || hi) && (c->per >> a & 1)) return fail(c, MM_EINVAL, "a PML needs a PEC axis (axis %d is periodic)", a);
+    c->pml_cells[2 * a] = lo;
+    c->pml_cells[2 * a + 1] = hi;
+    if (lo || hi) c->has_pml = true;
+  }
+  if (!c->has_pml) return MM_OK;
+  if (!(p->R0 > 0 && p->R0 < 1) || !(p->order >= 1)) return fail(c, MM_EINVAL, "bad PML grading (R0, order)");
+  c->pml_R0 = p->R0;
+  c->pml_order = p->order;
+  for (int a = 0; a < 3; ++a) {
+    const int n = n3[a];
+    std::vector<double>& kn = c->pml_kn[a];
+    std::vector<double>& kc = c->pml_kc[a];
+    kn.assign(n + 1, 0.0);
+    kc.assign(n, 0.0);
+    for (int side = 0; side < 2; ++side) {
+      const int thick = c->pml_cells[2 * a + side];
+      if (thick <= 0) continue;
+      const double L = thick * d3[a];
+      const double kmax = -(p->order + 1) * kC0 * std::log(p->R0) / (2.0 * L);
+      for (int q = 0; q <= n; ++q) {
+        const double depth = side == 0 ? (double)thick - q : q - (double)(n - thick);
+        if (depth > 0) kn[q] += kmax * std::pow(depth / thick, p->order);
+      }
+      for (int q = 0; q < n; ++q) {
+        const double depth = side == 0 ? (double)thick - (q + 0.5) : (q + 0.5) - (double)(n - thick);
+        if (depth > 0) kc[q] += kmax * std::pow(depth / thick, p->order);
+      }
+    }
+  }
+  return MM_OK;
+}
+
+// Device copies of the layer data and the split-part arrays; magnetic
+// faces with layer damping are rejected.
+mm_status upload_pml(mm_ctx* c) {
+  if (!c->has_pml) return MM_OK;
+  static const int PMa[3][2] = {{1, 2}, {2, 0}, {0, 1}};
+  for (size_t t = 0; t < c->h_idx.size(); ++t) {
+    const int pi = c->h_idx[t], f = c->h_fam[t];
+    const int k = pi / (c->px * c->py), rr = pi - k * c->px * c->py, j = rr / c->px, i = rr - j * c->px;
+    const int q[3] = {i, j, k};
+    const int p = PMa[f][0], m = PMa[f][1];
+    if (c->pml_kc[p][q[p]] > 0 || c->pml_kc[m][q[m]] > 0)
+      return fail(c, MM_EINVAL, "magnetic faces inside the PML are not supported (Sec. 3.2.3)");
+  }
+  for (int a = 0; a < 3; ++a) {
+    const std::vector<double>& kn = c->pml_kn[a];
+    const std::vector<double>& kc = c->pml_kc[a];
+    std::vector<double> dn(kn.size()), dc(kc.size());
+    std::vector<unsigned char> on(kn.size()), oc(kc.size());
+    for (size_t q = 0; q < kn.size(); ++q) {
+      dn[q] = std::exp(-kn[q] * c->dt / 2.0);
+      on[q] = kn[q] > 0;
+    }
+    for (size_t q = 0; q < kc.size(); ++q) {
+      dc[q] = std::exp(-kc[q] * c->dt / 4.0);
+      oc[q] = kc[q] > 0;
+    }
+    c->d_pdn[a] = (double*)dalloc(c, dn.size() * 8);
+    c->d_pdc[a] = (double*)dalloc(c, dc.size() * 8);
+    c->d_pon_n[a] = (unsigned char*)dalloc(c, on.size());
+    c->d_pon_c[a] = (unsigned char*)dalloc(c, oc.size());
+    c->PE[a] = dalloc(c, c->nelem * c->esz);
+    c->PH[a] = dalloc(c, c->nelem * c->esz);
+    if (!c->d_pdn[a] || !c->d_pdc[a] || !c->d_pon_n[a] || !c->d_pon_c[a] || !c->PE[a] || !c->PH[a])
+      return fail(c, MM_ENOMEM, "PML allocation failed");
+    HIPCHECK(c, hipMemcpy(c->d_pdn[a], dn.data(), dn.size() * 8, hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(c->d_pdc[a], dc.data(), dc.size() * 8, hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(c->d_pon_n[a], on.data(), on.size(), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(c->d_pon_c[a], oc.data(), oc.size(), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemset(c->PE[a], 0, c->nelem * c->esz));
+    HIPCHECK(c, hipMemset(c->PH[a], 0, c->nelem * c->esz));
+  }
+  return MM_OK;
+}
+
 // Launch order of a set of tiles: the dispatcher sends block b to XCD
 // b mod 8, so the tiles (in natural order, x fastest) are cut into 8 runs
 // of near-equal length and the runs interleaved; each XCD then works on a
@@ -764,10 +909,31 @@ mm_status build_tiles(mm_ctx* c) {
           if (ok) near[(q[0] / 64) + (size_t)c->tgx * ((q[1] / 4) + (size_t)c->tgy * (q[2] / c->tkc))] = 1;
         }
   }
-  std::vector<int> all, nr, fr;
+  // tiles holding layer entries: a cell within one cell of a layer
+  std::vector<unsigned char> pmlt(nt, 0);
+  if (c->has_pml) {
+    auto band = [&](int a, int q) {
+      const int lo = c->pml_cells[2 * a], hi = c->pml_cells[2 * a + 1];
+      return (lo > 0 && q <= lo) || (hi > 0 && q >= n3[a] - hi - 1);
+    };
+    for (size_t id = 0; id < nt; ++id) {
+      const int bx = (int)(id % c->tgx), by = (int)((id / c->tgx) % c->tgy), bz = (int)(id / ((size_t)c->tgx * c->tgy));
+      const int lo3[3] = {64 * bx, 4 * by, c->tkc * bz};
+      const int hi3[3] = {std::min(64 * bx + 64, c->nx), std::min(4 * by + 4, c->ny), std::min(c->tkc * (bz + 1), c->nz)};
+      bool hit = false;
+      for (int a = 0; a < 3 && !hit; ++a)
+        hit = band(a, lo3[a]) || band(a, hi3[a] - 1);
+      pmlt[id] = hit;
+    }
+  }
+  std::vector<int> all, nr, fr, pm;
   std::vector<unsigned char> far(nt, 0);
   c->cells_near = c->cells_far = 0;
   for (size_t id = 0; id < nt; ++id) {
+    if (pmlt[id]) {
+      pm.push_back((int)id);
+      continue;
+    }
     all.push_back((int)id);
     const int bx = (int)(id % c->tgx), by = (int)((id / c->tgx) % c->tgy), bz = (int)(id / ((size_t)c->tgx * c->tgy));
     const long long cells = (long long)std::min(64, c->nx - 64 * bx) * std::min(4, c->ny - 4 * by) *
@@ -784,16 +950,21 @@ mm_status build_tiles(mm_ctx* c) {
   all = xcd_order(all);
   nr = xcd_order(nr);
   fr = xcd_order(fr);
+  pm = xcd_order(pm);
+  c->n_pml = (int)pm.size();
+  c->d_tl_pml = (int*)dalloc(c, std::max<size_t>(pm.size(), 1) * sizeof(int));
+  if (!c->d_tl_pml) return fail(c, MM_ENOMEM, "tile-list allocation failed");
+  if (!pm.empty()) HIPCHECK(c, hipMemcpy(c->d_tl_pml, pm.data(), pm.size() * sizeof(int), hipMemcpyHostToDevice));
   c->n_all = (int)all.size();
   c->n_near = (int)nr.size();
   c->n_far = (int)fr.size();
-  c->d_tl_all = (int*)dalloc(c, all.size() * sizeof(int));
+  c->d_tl_all = (int*)dalloc(c, std::max<size_t>(all.size(), 1) * sizeof(int));
   c->d_tl_near = (int*)dalloc(c, nr.size() * sizeof(int));
   c->d_tl_far = (int*)dalloc(c, fr.size() * sizeof(int));
   c->d_far = (unsigned char*)dalloc(c, nt);
   if (!c->d_tl_all || !c->d_tl_near || !c->d_tl_far || !c->d_far)
     return fail(c, MM_ENOMEM, "tile-list allocation failed");
-  HIPCHECK(c, hipMemcpy(c->d_tl_all, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice));
+  if (!all.empty()) HIPCHECK(c, hipMemcpy(c->d_tl_all, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice));
   if (!nr.empty()) HIPCHECK(c, hipMemcpy(c->d_tl_near, nr.data(), nr.size() * sizeof(int), hipMemcpyHostToDevice));
   if (!fr.empty()) HIPCHECK(c, hipMemcpy(c->d_tl_far, fr.data(), fr.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPCHECK(c, hipMemcpy(c->d_far, far.data(), nt, hipMemcpyHostToDevice));
@@ -1050,7 +1221,9 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
   HIPCHECK(c, hipHostGetDevicePointer((void**)&c->d_ring, c->h_ring, 0));
 
   {
-    mm_status ts = build_tiles(c);
+    mm_status ts = upload_pml(c);
+    if (ts) return ts;
+    ts = build_tiles(c);
     if (ts) return ts;
   }
 
@@ -1145,6 +1318,17 @@ mm_status mm_init(mm_ctx** out, const mm_grid* g, double dt, const mm_materials*
     return bad("iteration options");
   if (opt->prec != MM_FP64 && opt->prec != MM_FP32) return bad("precision");
   if (opt->scheme != 0 && opt->scheme != 1 && opt->scheme != 2) return bad("scheme");
+  if (opt->pml) {
+    const int n3[3] = {g->nx, g->ny, g->nz};
+    bool any = false;
+    for (int a = 0; a < 3; ++a) {
+      const int lo = opt->pml->cells[2 * a], hi = opt->pml->cells[2 * a + 1];
+      if (lo < 0 || hi < 0 || lo + hi >= n3[a]) return bad("PML thickness");
+      if ((lo || hi) && g->bc[a] == MM_BC_PERIODIC) return bad("PML on a periodic axis");
+      any = any || lo || hi;
+    }
+    if (any && (!(opt->pml->R0 > 0 && opt->pml->R0 < 1) || !(opt->pml->order >= 1))) return bad("PML grading");
+  }
   const size_t ncells = (size_t)g->nx * g->ny * g->nz;
   if (!finite_nonneg(mat->eps_r, ncells, true) || !finite_nonneg(mat->mu_r, ncells, true) ||
       !finite_nonneg(mat->sigma, ncells, false) || !finite_nonneg(mat->Ms, ncells, false) ||
@@ -1187,7 +1371,8 @@ mm_status mm_init(mm_ctx** out, const mm_grid* g, double dt, const mm_materials*
   c->ualloc = opt->dev_alloc;
   c->ufree = opt->dev_free;
   c->actx = opt->alloc_ctx;
-  mm_status s = build(c, mat, src);
+  mm_status s = setup_pml(c, opt->pml);
+  if (s == MM_OK) s = build(c, mat, src);
   if (s == MM_OK) {
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) s = fail(c, MM_EDEVICE, "init: %s", hipGetErrorString(e));
@@ -1472,7 +1657,7 @@ mm_status mm_layout(const mm_ctx* c, int64_t out[8]) {
   out[4] = c->cells_far;
   out[5] = c->tkc;
   out[6] = c->nmat;
-  out[7] = 0;
+  out[7] = c->n_pml;
   return MM_OK;
 }
 
@@ -1484,6 +1669,7 @@ mm_status mm_adjoint_enable(mm_ctx* c, int32_t checkpoint_every, int32_t inner_e
   if (c->step != 0) return fail(c, MM_ESTATE, "the adjoint must be enabled before the first step");
   if (c->mu) return fail(c, MM_EINVAL, "the adjoint supports mu_r = 1 only");
   if (c->scheme != 2) return fail(c, MM_EINVAL, "the adjoint supports the second-order scheme only");
+  if (c->has_pml) return fail(c, MM_EINVAL, "the adjoint does not support an open boundary");
   c->ckpt_every = checkpoint_every;
   c->ckpt_inner = inner_every;
   return MM_OK;

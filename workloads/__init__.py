@@ -83,6 +83,7 @@ class Config:
     # initial fields (ABI layout, staggered extents); None -> zero
     E_init: Optional[list] = None
     H_init: Optional[list] = None
+    pml: Optional[tuple] = None          # open boundary: (cells[6], R0, order)
 
     @property
     def cells(self) -> int:

@@ -67,6 +67,11 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"HIP library {path} is missing; run `python -m paper_2103_12819_amd.build`")
+    # torch ships its own HIP runtime; load it first so that libmm.so binds to
+    # that one (its libamdhip64.so.7 dependency is then already loaded) and
+    # the process holds a single HIP runtime, whatever the caller imported
+    # first.  Loading libmm.so first would pull in a second runtime.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P = C.c_void_p
     lib.mm_init.argtypes = [C.POINTER(P), C.POINTER(mm_grid), C.c_double, C.POINTER(mm_materials),

@@ -326,6 +326,28 @@ def scale1024(seed: int = 0, steps: int = 500, n=(1024, 512, 512)) -> Config:
     return cfg
 
 
+def air_waveguide(steps: int = 80000, pml_cells: int = 64) -> Config:
+    """The air-filled X-band waveguide of Sec. 5.2.1: W = 14.95 mm (x),
+    h = 10.16 mm (y), L = 500 mm (z) on 512 x 4 x 512 cells, PEC side walls,
+    PEC at the z = +L/2 end and an open boundary (PML of `pml_cells` cells)
+    at z = -L/2; CFL 0.8.  A TE10 current sheet Jy ~ sin(pi x / W) one cell
+    inside the PEC end carries the modulated Gaussian pulse (f0 = 10.5 GHz,
+    Tp = 1/f0, peak at 3 Tp).  Ey is sampled along the centre line
+    x = W/2, all z."""
+    W_, h_, L_ = 14.95e-3, 10.16e-3, 500e-3
+    n = (512, 4, 512)
+    d = (W_ / n[0], h_ / n[1], L_ / n[2])
+    cfg = Config(name="airwg", n=n, d=d, dt=cfl_dt(0.8, *d), steps=steps)
+    prof = np.zeros(edge_shape(n, (False,) * 3, 1))
+    xi = np.arange(n[0] + 1) * d[0]
+    prof[n[2] - 1, :, :] = np.sin(np.pi * xi / W_)[None, :]
+    f0 = 10.5e9
+    cfg.source = Source(1, prof, f0, 1.0 / f0, 3.0 / f0)
+    cfg.pml = ((0, 0, 0, 0, pml_cells, 0), 1e-6, 3.0)
+    cfg.probes = [Probe(0, FIELD_ID["Ey"], n[0] // 2, n[1] // 2, k) for k in range(n[2] + 1)]
+    return cfg
+
+
 def convergence_cube(N: int, side: float = 0.2, tol: float = 1e-6) -> Config:
     """The coupled convergence problem of Sec. 5.1 on an N^3 grid.
 

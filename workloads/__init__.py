@@ -348,6 +348,44 @@ def air_waveguide(steps: int = 80000, pml_cells: int = 64) -> Config:
     return cfg
 
 
+def tunable_filter(steps: int = 320000, pml_cells: int = 64, gap: int = 16, n=(1024, 4, 512)) -> Config:
+    """The magnetically tunable filter of Sec. 5.2.2: the waveguide of
+    air_waveguide() with a YIG slab 0.45 mm thick against the x = 0 side
+    wall, over the full height and along the guide (Ms = 1.3926e5 A/m,
+    alpha = 0.0051, eps_r = 13), bias H0 = 2.2998e5 A/m along y, M along y;
+    1024 x 4 x 512 cells, CFL 0.8.  The slab stops `gap` cells short of the
+    open layer at z = -L/2 (magnetic material inside the layer is not
+    supported).  320,000 steps are 12.5 ns, four decay times of the damped
+    precession (1 / (alpha omega) ~ 3 ns): the spectrum has settled."""
+    W_, h_, L_ = 14.95e-3, 10.16e-3, 500e-3
+    d = (W_ / n[0], h_ / n[1], L_ / n[2])
+    cfg = Config(name="mtf", n=n, d=d, dt=cfl_dt(0.8, *d), steps=steps)
+    shp = (n[2], n[1], n[0])
+    t = int(round(0.45e-3 / d[0]))
+    eps = np.ones(shp)
+    Ms = np.zeros(shp)
+    alpha = np.zeros(shp)
+    z0 = pml_cells + gap
+    eps[z0:, :, :t] = 13.0
+    Ms[z0:, :, :t] = 1.3926e5
+    alpha[z0:, :, :t] = 0.0051
+    m0 = np.zeros((3,) + shp)
+    m0[1] = 1.0
+    cfg.eps_r, cfg.Ms, cfg.alpha = eps, Ms, alpha
+    cfg.gamma = np.full(shp, GAMMA_E)
+    cfg.m0_dir = m0
+    cfg.H0 = (0.0, 2.2998e5, 0.0)
+    cfg.tol = 1e-10
+    prof = np.zeros(edge_shape(n, (False,) * 3, 1))
+    xi = np.arange(n[0] + 1) * d[0]
+    prof[n[2] - 1, :, :] = np.sin(np.pi * xi / W_)[None, :]
+    f0 = 10.5e9
+    cfg.source = Source(1, prof, f0, 1.0 / f0, 3.0 / f0)
+    cfg.pml = ((0, 0, 0, 0, pml_cells, 0), 1e-6, 3.0)
+    cfg.probes = [Probe(0, FIELD_ID["Ey"], n[0] // 2, n[1] // 2, k) for k in range(n[2] + 1)]
+    return cfg
+
+
 def convergence_cube(N: int, side: float = 0.2, tol: float = 1e-6) -> Config:
     """The coupled convergence problem of Sec. 5.1 on an N^3 grid.
 

@@ -33,20 +33,101 @@ KERNELS_H = os.path.join(ROOT, "paper_2103_12819_amd", "csrc", "kernels.h")
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
-def measured_traffic(kernel):
+def _kernels_h_sha256():
+    import hashlib
+    return hashlib.sha256(open(KERNELS_H, "rb").read()).hexdigest()
+
+
+def measured_traffic(kernel, cells_per_launch):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE runs (scaled by a plain copy's reading), or None when the
-    kernel source has changed since they were taken."""
-    import hashlib
+    kernel source has changed since they were taken or the record covers a
+    different number of cells per launch."""
     try:
         rec = json.load(open(TRAFFIC_JSON))
-        src = open(KERNELS_H, "rb").read()
-    except OSError:
+        sha = _kernels_h_sha256()
+    except (OSError, ValueError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec.get("kernels_h_sha256"):
+    if sha != rec.get("kernels_h_sha256"):
         return None
     k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k["traffic_bytes_per_launch"]
+    if k is None or k.get("cells_per_launch") != cells_per_launch:
+        return None
+    return k["traffic_bytes_per_launch"]
+
+
+# kernel names in the counter databases -> the names used here (h_far is the
+# two-half-step instantiation of h_bulk)
+_PMC_NAMES = (("e_update", "e_update<double"), ("h_far", "h_bulk<double, false, 2>"),
+              ("h_bulk", "h_bulk<double, false, 1>"), ("hm_pre", "hm_pre<double"),
+              ("hm_step", "hm_step<double"), ("hm_commit", "hm_commit<double"),
+              ("probe_flux", "probe_flux<double"))
+
+
+def write_traffic_record(pmc_dir, workload="filter512"):
+    """Turn the four rocprofv3 counter runs under `pmc_dir` (FETCH_SIZE and
+    WRITE_SIZE of `bench.py --start 0 --steps 3 --warmup 1 --no-cpu --no-fp32
+    --no-adjoint` and of `bench.py --calibrate-copy`) into the traffic record
+    and a markdown table; CPU only.  Counter values are KiB per dispatch."""
+    import sqlite3
+
+    def per_kernel(db):
+        rows = sqlite3.connect(db).execute(
+            "select kernel_name, counter_name, value from counters_collection").fetchall()
+        acc = {}
+        for name, _ctr, val in rows:
+            acc.setdefault(name, []).append(float(val))
+        return {n: (len(v), sum(v) / len(v)) for n, v in acc.items()}
+
+    def one(ctr, kind):
+        d = os.path.join(pmc_dir, f"{ctr}_{kind}")
+        dbs = [os.path.join(d, f) for f in os.listdir(d) if f.endswith("_results.db")]
+        if len(dbs) != 1:
+            raise SystemExit(f"expected one *_results.db under {d}, found {dbs}")
+        return per_kernel(dbs[0])
+
+    copy_bytes = 1 << 30
+    scale = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        c = one(ctr, "copy")
+        (n, kib), = [v for k, v in c.items() if "copyBuffer" in k]
+        scale[ctr] = copy_bytes / (kib * 1024)
+    cfg = W.CONFIGS[workload]()
+    tiles = json.load(open(os.path.join(pmc_dir, "tiles.json")))
+    cells = {"e_update": cfg.cells, "h_far": tiles["far_cells"]}
+    fetch, write = one("FETCH_SIZE", "bench"), one("WRITE_SIZE", "bench")
+    rec = {"kernels_h_sha256": _kernels_h_sha256(),
+           "workload": f"{cfg.name} {cfg.n[0]}x{cfg.n[1]}x{cfg.n[2]} fp64",
+           "command": "bench.py --start 0 --steps 3 --warmup 1 --no-cpu --no-fp32 --no-adjoint",
+           "fetch_scale": scale["FETCH_SIZE"], "write_scale": scale["WRITE_SIZE"], "kernels": {}}
+    lines = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read GB | write GB | "
+             "algorithmic GB | traffic / algorithmic |", "|---|---|---|---|---|---|---|---|"]
+    for short, pat in _PMC_NAMES:
+        fk = [k for k in fetch if pat in k]
+        wk = [k for k in write if pat in k]
+        if len(fk) != 1 or len(wk) != 1:
+            continue
+        nf, f = fetch[fk[0]]
+        _, w = write[wk[0]]
+        rd, wr = f * 1024 * scale["FETCH_SIZE"], w * 1024 * scale["WRITE_SIZE"]
+        ent = {"instantiation": fk[0].split("(")[0], "dispatches": nf, "read_bytes_per_launch": int(rd),
+               "write_bytes_per_launch": int(wr), "traffic_bytes_per_launch": int(rd + wr)}
+        algo = "-"
+        ratio = "-"
+        if short in cells:
+            ent["cells_per_launch"] = cells[short]
+            b = bytes_per_cell(short, 8, tiles, cfg) * cells[short]
+            ent["algorithmic_bytes_per_launch"] = int(b)
+            algo = f"{b / 1e9:.3f}"
+            ratio = f"{(rd + wr) / b:.3f}"
+        rec["kernels"][short] = ent
+        lines.append(f"| `{ent['instantiation']}` | {nf} | {f:.1f} | {w:.1f} | {rd / 1e9:.3f} | "
+                     f"{wr / 1e9:.3f} | {algo} | {ratio} |")
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(f"fetch scale {scale['FETCH_SIZE']:.4f}, write scale {scale['WRITE_SIZE']:.4f}")
+    print("\n".join(lines))
 
 
 BULK_KERNELS = ("h_bulk", "h_far", "e_update")
@@ -232,7 +313,14 @@ def main():
                          "~250 GB of device memory)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (scale reference for HBM counters)")
+    ap.add_argument("--tiles-json", default=None,
+                    help="write the workload's tile counts to this file and exit (GPU)")
+    ap.add_argument("--traffic-record", default=None, metavar="PMC_DIR",
+                    help="write profiles/pmc_traffic.json from the counter runs under PMC_DIR (CPU)")
     args = ap.parse_args()
+    if args.traffic_record:
+        write_traffic_record(args.traffic_record, args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU slab decomposition is described in the design notes only)",
@@ -246,11 +334,23 @@ def main():
     if args.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(5):
             dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
         print(json.dumps({"calibrate_copy_bytes_read": src.numel() * 4, "bytes_written": dst.numel() * 4,
-                          "launches": 5}), flush=True)
+                          "launches": 6, "avg_ms": round(ms, 4),
+                          "GB/s": round(2 * src.numel() * 4 / (ms / 1e3) / 1e9, 1)}), flush=True)
+        return
+    if args.tiles_json:
+        import paper_2103_12819_amd as mm
+        sim = mm.from_config(W.CONFIGS[args.workload](), with_probes=False)
+        json.dump(sim.tiles(), open(args.tiles_json, "w"))
+        sim.close()
         return
 
     cfg = W.CONFIGS[args.workload]()
@@ -267,7 +367,7 @@ def main():
     dom_cells = cells_per_launch(dom, kern64, info64["tiles"], cells, args.steps)
     algo_bytes = int(round(bytes_per_cell(dom, 8, info64["tiles"], cfg) * dom_cells))
     achieved = algo_bytes / avg_s / 1e9
-    traffic = measured_traffic(dom)
+    traffic = measured_traffic(dom, dom_cells)
     print(f"[bench] fp64 {per_step:.3f} ms/step, {value:.1f} Mcell/s, kernels {kern64}", flush=True)
 
     out = {

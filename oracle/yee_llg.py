@@ -25,6 +25,9 @@ Coupled Electrodynamics-Micromagnetics Solver".
     matched layer (Berenger) whose split parts take the macroscopic update
     and are damped before and after it (the two-step time-centred form the
     paper uses), with a graded damping rate matched for E and H.
+  * Sec. 3.2 (hard_sources=...): hard sources, a field component overwritten
+    with a prescribed waveform after each of its updates (E after Step 2,
+    H after each Faraday half step, on faces that do not evolve M).
   * Sec. 3.2.1 Steps 1 and 3 (scheme=1): the first-order scheme, an
     explicit step of the LLG in Landau-Lifshitz form (eq:LLG_scalar, with
     gamma_L = gamma / (1 + alpha^2)) then N(M) and eq:H_update /
@@ -39,7 +42,11 @@ closed form is used with signed gamma (kappa = mu0*gamma*dt/4), identical to
 the printed |gamma| form for gamma < 0; edges average the 4 adjacent cells
 and faces the 2 adjacent cells (clamped at PEC walls); alpha and gamma on a
 face average over its magnetic neighbour cells only; magnetic faces lying on
-a PEC wall are not evolved; the soft current enters Step 2 at t^{n+1/2}.
+a PEC wall are not evolved; the soft current enters Step 2 at t^{n+1/2};
+a hard source holds on the bounding box of its profile's nonzero interior
+entries and takes g(t^{n+1}) after Step 2 (E), g(t^{n+1/2}) after Step 1 and
+g(t^{n+1}) after Step 3 (H), an H source replacing the non-magnetic Faraday
+value before the iterations read it.
 
 Arrays are indexed [i, j, k] internally; inputs and outputs use the host
 layout of the library (x fastest, numpy shape (nz', ny', nx')).
@@ -169,6 +176,8 @@ class Simulation:
     None, or (cells, R0, order) with cells = (x_lo, x_hi, y_lo, y_hi, z_lo,
     z_hi) layer thicknesses on PEC axes, the normal-incidence reflection
     target R0 of the grading and its polynomial order.
+    `hard_sources`: a list of (field, profile, f0, Tp, t0) hard sources
+    (field 0-2: Ex, Ey, Ez; 3-5: Hx, Hy, Hz; see add_hard_source).
     `dtype` complex128 runs the same arithmetic on complex numbers (all
     decisions use real parts), for complex-step derivatives in the tests.
     """
@@ -177,7 +186,7 @@ class Simulation:
                  alpha=None, gamma=None, m0_dir=None, H0=(0.0, 0.0, 0.0),
                  source=None, periodic=(False, False, False), tol=1e-10,
                  max_iter=100, fixed_iter=0, raise_on_noconv=False, dtype=np.float64, scheme=2,
-                 pml=None):
+                 pml=None, hard_sources=()):
         self.dtype = np.dtype(dtype)
         assert scheme in (1, 2)
         self.scheme = int(scheme)
@@ -223,7 +232,11 @@ class Simulation:
             prof = to_ijk(prof, self.dtype)
             assert prof.shape == self.edge_shape(comp)
             self.src = (int(comp), prof * self.e_interior[comp], float(f0), float(Tp), float(t0))
+        self.hard = []           # (field, support mask, profile, f0, Tp, t0)
+        for hs in hard_sources:
+            self.add_hard_source(*hs)
         self.step_count = 0
+        self._t_sub = 0.0        # time level the current sub-step ends at (hard H sources)
         self._E_for_C = None     # the E whose curl the current sub-step uses (for the PML split)
         self.iters = []          # iterations used by every sub-step, in order
         self.noconv = False
@@ -246,6 +259,76 @@ class Simulation:
             m[0] = False
             m[-1] = False
         return m
+
+    # ---- hard sources (Sec. 3.2) ------------------------------------------
+    def add_hard_source(self, field, profile, f0, Tp, t0):
+        """Hard source on component `field` (0-2: Ex, Ey, Ez; 3-5: Hx, Hy, Hz):
+        after every update of that component, the entries inside the bounding
+        box of the nonzero interior entries of `profile` (host layout, the
+        component's staggered extent) are set to profile * g(t), g the pulse
+        of Sec. 5.2.1.  Interior means not pinned by a PEC wall; pinned
+        entries inside the box stay zero.  H sources may not hold evolving
+        magnetic faces, and no source may reach into an open-boundary layer."""
+        field = int(field)
+        assert 0 <= field < 6
+        c = field % 3
+        is_e = field < 3
+        shp = self.edge_shape(c) if is_e else self.face_shape(c)
+        prof = to_ijk(profile, self.dtype)
+        assert prof.shape == shp
+        interior = self.e_interior[c] if is_e else self.h_interior[c]
+        nz = np.argwhere((prof != 0) & interior)
+        if len(nz) == 0:
+            raise ValueError("a hard source needs a nonzero interior profile entry")
+        lo, hi = nz.min(axis=0), nz.max(axis=0) + 1
+        box = np.zeros(shp, dtype=bool)
+        box[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] = True
+        mask = box & interior
+        if not is_e and np.any(mask & self.evolve[c]):
+            raise ValueError("a hard H source may not hold evolving magnetic faces")
+        if self.pml_cells is not None:
+            for a in range(3):
+                lo_t, hi_t = self.pml_cells[2 * a], self.pml_cells[2 * a + 1]
+                # positions along axis a in cells: cell centres where the
+                # component is cell-centred, nodes elsewhere
+                cell_axis = (a == c) if is_e else (a != c)
+                pos = np.arange(shp[a]) + (0.5 if cell_axis else 0.0)
+                bad = ((lo_t > 0) & (pos < lo_t)) | ((hi_t > 0) & (pos > self.n[a] - hi_t))
+                if np.any(bad[lo[a]:hi[a]]):
+                    raise ValueError("a hard source may not reach into an open-boundary layer")
+        self.hard.append((field, mask, prof, float(f0), float(Tp), float(t0)))
+
+    def add_surface_current(self, axis, side, comp, profile, f0, Tp, t0):
+        """Surface current J_s (A/m) along `comp` on the PEC wall normal to
+        `axis` at its low (side 0) or high (side 1) end (Sec. 5.2.1): the
+        boundary condition n x H = J_s, n the unit normal into the domain,
+        fixes the tangential H at the wall to J_s x n.  It is held, as a hard
+        source, on the tangential-H faces half a cell inside the wall.
+        `profile`: host layout on component `comp`'s edge array; the entries
+        on the wall plane are used."""
+        axis, side, comp = int(axis), int(side), int(comp)
+        assert axis != comp and not self.per[axis] and side in (0, 1)
+        h = 3 - axis - comp
+        # e_comp x n, n = -e_axis at the high wall, +e_axis at the low wall
+        perm = {(0, 1, 2): 1, (1, 2, 0): 1, (2, 0, 1): 1, (0, 2, 1): -1, (2, 1, 0): -1, (1, 0, 2): -1}
+        sign = perm[(comp, axis, h)] * (1 if side == 0 else -1)
+        J = to_ijk(profile, self.dtype)
+        assert J.shape == self.edge_shape(comp)
+        Hp = np.zeros(self.face_shape(h), dtype=self.dtype)
+        wall_node = 0 if side == 0 else self.n[axis]
+        first_cell = 0 if side == 0 else self.n[axis] - 1
+        src = [slice(None)] * 3
+        dst = [slice(None)] * 3
+        src[axis] = wall_node
+        dst[axis] = first_cell
+        Hp[tuple(dst)] = sign * J[tuple(src)]
+        self.add_hard_source(3 + h, to_host(Hp), f0, Tp, t0)
+
+    def _apply_hard(self, arr, field, t):
+        for fid, mask, prof, f0, Tp, t0 in self.hard:
+            if fid == field:
+                arr = np.where(mask, prof * waveform(t, f0, Tp, t0), arr)
+        return arr
 
     # ---- init: materials to edges and faces (Sec. 3.1) -------------------
     def _prepare(self, m0):
@@ -389,12 +472,14 @@ class Simulation:
 
     def _prepare_pml(self, pml):
         self.pml = None
+        self.pml_cells = None
         if pml is None:
             return
         cells, R0, order = pml
         cells = tuple(int(v) for v in cells)
         if not any(cells):
             return
+        self.pml_cells = cells
         c0 = 299792458.0
         node_k, cent_k = [], []
         for a in range(3):
@@ -492,6 +577,7 @@ class Simulation:
             q = Hs[f] + M[f] - (h / MU0) * C[f]
             H_nonmag = np.where(self.h_interior[f], Hs[f] - (h / self.mu_f[f]) * C[f], Hs[f])
             H_nonmag = self._pml_h(Hs, H_nonmag, f, h, self._E_for_C)
+            H_nonmag = self._apply_hard(H_nonmag, 3 + f, self._t_sub)
             Hn_all.append(np.where(ev, q - Mn[f], H_nonmag))
             Mn_all.append(Mn)
         self.H = Hn_all
@@ -512,8 +598,9 @@ class Simulation:
         H_nonmag, q, b, dvec, kappa = [], [], [], [], []
         for f in range(3):
             # faces with Ms = 0: Faraday with the local mu (eq:Faraday3)
-            H_nonmag.append(self._pml_h(Hs, np.where(self.h_interior[f], Hs[f] - (h / self.mu_f[f]) * C[f], Hs[f]),
-                                        f, h, self._E_for_C))
+            H_nonmag.append(self._apply_hard(
+                self._pml_h(Hs, np.where(self.h_interior[f], Hs[f] - (h / self.mu_f[f]) * C[f], Hs[f]),
+                            f, h, self._E_for_C), 3 + f, self._t_sub))
             # iteration-invariant parts of eq:llg_tra5/6 and eq:iterate_H
             kap = MU0 * self.gamma_f[f] * self.dt / 4.0
             He = self.H_eff(Hs, f)
@@ -594,7 +681,7 @@ class Simulation:
                 Mn = dm * (self.ca[c] * (dm * Mpart) - self.cb[c] * Tm)
                 self.pml["PE"][c] = np.where(on, Pn, P)
                 Eplain = np.where(on, Pn + Mn, Eplain)
-            self.E[c] = Eplain
+            self.E[c] = self._apply_hard(Eplain, c, (self.step_count + 1.0) * self.dt)
 
     # ---- one full step n -> n+1 --------------------------------------------
     def step(self, nsteps=1, tape=None):
@@ -604,10 +691,14 @@ class Simulation:
             rec = None
             if tape is not None:
                 rec = {"n": self.step_count, "E0": [a.copy() for a in self.E], "tr1": {}, "tr3": {}}
+            if rec is not None and self.hard:
+                raise ValueError("the reverse sweep does not cover hard sources")
             self._E_for_C = self.E
+            self._t_sub = (self.step_count + 0.5) * self.dt
             self.hm_substep(self.curl_E(self.E), trace=None if rec is None else rec["tr1"])  # Step 1
             self.e_update()                                                                  # Step 2
             self._E_for_C = self.E
+            self._t_sub = (self.step_count + 1.0) * self.dt
             self.hm_substep(self.curl_E(self.E), trace=None if rec is None else rec["tr3"])  # Step 3
             self.step_count += 1
             if rec is not None:
@@ -668,11 +759,15 @@ def from_config(cfg, fixed_iter=0, with_probes=True, **kw):
     if cfg.source is not None:
         s = cfg.source
         src = (s.comp, s.profile, s.f0, s.Tp, s.t0)
+    hard = [(h.field, h.profile, h.f0, h.Tp, h.t0) for h in cfg.hard_sources]
     sim = Simulation(cfg.n, cfg.d, cfg.dt, eps_r=cfg.eps_r, sigma=cfg.sigma,
                      mu_r=cfg.mu_r, Ms=cfg.Ms, alpha=cfg.alpha, gamma=cfg.gamma,
                      m0_dir=cfg.m0_dir, H0=cfg.H0, source=src, periodic=cfg.periodic,
                      tol=cfg.tol, max_iter=cfg.max_iter, fixed_iter=fixed_iter,
-                     **({"pml": cfg.pml} if cfg.pml is not None else {}), **kw)
+                     **({"pml": cfg.pml} if cfg.pml is not None else {}),
+                     **({"hard_sources": hard} if hard else {}), **kw)
+    for sc in cfg.surface_currents:
+        sim.add_surface_current(sc.axis, sc.side, sc.comp, sc.profile, sc.f0, sc.Tp, sc.t0)
     if cfg.E_init is not None or cfg.H_init is not None:
         sim.set_fields(cfg.E_init, cfg.H_init)
     if with_probes:

@@ -46,6 +46,26 @@ class Source:
 
 
 @dataclass
+class HardSource:
+    field: int                   # 0-2: Ex, Ey, Ez; 3-5: Hx, Hy, Hz
+    profile: np.ndarray          # amplitude (V/m or A/m) on that component's array
+    f0: float
+    Tp: float
+    t0: float
+
+
+@dataclass
+class SurfaceCurrent:
+    axis: int                    # normal of the PEC wall
+    side: int                    # 0: low end, 1: high end of that axis
+    comp: int                    # direction of J_s
+    profile: np.ndarray          # J_s (A/m) on component comp's edge array (wall plane used)
+    f0: float
+    Tp: float
+    t0: float
+
+
+@dataclass
 class Probe:
     kind: int                    # 0: point sample, 1: x-plane Poynting flux
     field: int = 0               # see FIELD_NAMES
@@ -84,6 +104,8 @@ class Config:
     E_init: Optional[list] = None
     H_init: Optional[list] = None
     pml: Optional[tuple] = None          # open boundary: (cells[6], R0, order)
+    hard_sources: list = field(default_factory=list)       # HardSource entries
+    surface_currents: list = field(default_factory=list)   # SurfaceCurrent entries
 
     @property
     def cells(self) -> int:

@@ -88,6 +88,38 @@ typedef struct {
   double f0, Tp, t0;
 } mm_source;
 
+/* Hard source (Sec. 3.2: a hard source is imposed on its field right after
+ * that field's update).  After every update of component `field` (0-2: Ex,
+ * Ey, Ez after Step 2, value at t^{n+1}; 3-5: Hx, Hy, Hz after the Faraday
+ * half step of Step 1, at t^{n+1/2}, and of Step 3, at t^{n+1}, before the
+ * H-M iteration reads it), the entries inside the bounding box of the
+ * nonzero interior entries of `profile` are set to profile * g(t), g the
+ * pulse of mm_source.  `profile` is a host array on the component's
+ * staggered extent (V/m or A/m); entries pinned by a PEC wall (tangential E,
+ * normal H) stay zero; zeros inside the box are held at zero. */
+typedef struct {
+  int32_t field;
+  const double *profile;
+  double f0, Tp, t0;
+} mm_hard_source;
+
+/* Surface current on a PEC wall (Sec. 5.2.1: the excitation is the surface
+ * current density J_s on the wall, imposed through the jump of tangential H
+ * there).  J_s (A/m) runs along `comp` on the wall normal to `axis` at its
+ * low (side 0) or high (side 1) end.  The boundary condition n x H = J_s,
+ * n the unit normal into the domain, gives the tangential H = J_s x n; it is
+ * held, as a hard source, on the tangential-H faces half a cell inside the
+ * wall (the nearest H samples on the Yee grid).  `profile`: host array on
+ * component `comp`'s edge extent; only its entries on the wall plane are
+ * read. */
+typedef struct {
+  int32_t axis, side, comp;
+  const double *profile;
+  double f0, Tp, t0;
+} mm_surface_current;
+
+#define MM_MAX_HARD 8
+
 /* Open boundary (Sec. 3.2.3): a split-field perfectly matched layer.
  * cells[2a], cells[2a+1]: thickness in cells of the layer at the low / high
  * end of axis a (a PEC axis; 0: none; the wall behind it stays PEC).  Each
@@ -152,6 +184,21 @@ typedef struct {
 } mm_probe_desc;
 
 mm_status mm_add_probe(mm_ctx *c, const mm_probe_desc *d, int32_t *id);
+
+/* Add a hard source (see mm_hard_source).  Before the first step only
+ * (MM_ESTATE after).  MM_EINVAL: field outside 0-5, a null profile, no
+ * nonzero interior entry, an H source whose box holds an evolving magnetic
+ * face, a box reaching into an open-boundary layer (an index whose position
+ * along a layer axis, the node or the cell centre, lies inside the layer),
+ * more than MM_MAX_HARD sources (surface currents included), or the adjoint
+ * enabled (it does not cover hard sources).  An H source moves the tiles its
+ * box touches out of the fused Faraday pass. */
+mm_status mm_add_hard_source(mm_ctx *c, const mm_hard_source *s);
+
+/* Add a surface current (see mm_surface_current); conditions as for
+ * mm_add_hard_source, plus MM_EINVAL for a periodic `axis`, comp == axis or
+ * side outside {0, 1}. */
+mm_status mm_add_surface_current(mm_ctx *c, const mm_surface_current *s);
 
 /* Copy up to `cap` recorded values of probe `id` (one FP64 per step, oldest
  * first) to host `out` (may be NULL to query); *n_written gets the number
@@ -219,7 +266,8 @@ mm_status mm_layout(const mm_ctx *c, int64_t out[8]);
  * segment from its checkpoint and leaves the context's state, step count
  * and probes as they were.  Requirements: mu_r = 1 everywhere (MM_EINVAL
  * from mm_adjoint_enable otherwise), a flux probe, at most 16 iterations
- * per sub-step (MM_ESTATE otherwise).  Synchronises the stream. */
+ * per sub-step (MM_ESTATE otherwise), no hard source or surface current
+ * (MM_EINVAL from either side).  Synchronises the stream. */
 mm_status mm_adjoint_enable(mm_ctx *c, int32_t checkpoint_every, int32_t inner_every);
 mm_status mm_adjoint(mm_ctx *c, int32_t probe_id, double *grad_eps_r, double *grad_Ms);
 

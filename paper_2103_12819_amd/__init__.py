@@ -157,6 +157,23 @@ class Sim:
                                            C.byref(pid)))
         return pid.value
 
+    def add_hard_source(self, field, profile, f0, Tp, t0):
+        """Hard source on field id 0-5 (Ex..Hz): see mm_add_hard_source."""
+        fid = FIELD_ID[field] if isinstance(field, str) else int(field)
+        prof = np.ascontiguousarray(profile, dtype=np.float64)
+        if prof.shape != self.extent(fid):
+            raise ValueError(f"profile shape {prof.shape} != {self.extent(fid)}")
+        self._check(self._lib.mm_add_hard_source(self._ctx, C.byref(N.mm_hard_source(fid, _dp(prof), f0, Tp, t0))))
+
+    def add_surface_current(self, axis, side, comp, profile, f0, Tp, t0):
+        """Surface current J_s along `comp` on the PEC wall normal to `axis`
+        (side 0: low end, 1: high end): see mm_add_surface_current."""
+        prof = np.ascontiguousarray(profile, dtype=np.float64)
+        if prof.shape != self.extent(int(comp)):
+            raise ValueError(f"profile shape {prof.shape} != {self.extent(int(comp))}")
+        self._check(self._lib.mm_add_surface_current(
+            self._ctx, C.byref(N.mm_surface_current(axis, side, comp, _dp(prof), f0, Tp, t0))))
+
     def step(self, n=1):
         self._check(self._lib.mm_step(self._ctx, int(n)))
 
@@ -276,6 +293,10 @@ def from_config(cfg, precision="fp64", fixed_iter=0, with_probes=True, **kw):
               alpha=cfg.alpha, gamma=cfg.gamma, m0_dir=cfg.m0_dir, H0=cfg.H0, source=src,
               periodic=cfg.periodic, precision=precision, tol=cfg.tol, max_iter=cfg.max_iter,
               fixed_iter=fixed_iter, **({"pml": cfg.pml} if cfg.pml is not None else {}), **kw)
+    for h in cfg.hard_sources:
+        sim.add_hard_source(h.field, h.profile, h.f0, h.Tp, h.t0)
+    for sc in cfg.surface_currents:
+        sim.add_surface_current(sc.axis, sc.side, sc.comp, sc.profile, sc.f0, sc.Tp, sc.t0)
     if cfg.E_init is not None or cfg.H_init is not None:
         sim.set_fields(cfg.E_init, cfg.H_init)
     if with_probes:

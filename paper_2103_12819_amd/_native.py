@@ -13,7 +13,8 @@ STATUS_NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EDEVICE",
 MM_BC_PEC, MM_BC_PERIODIC = 0, 1
 MM_FP64, MM_FP32 = 0, 1
 
-EXPORTED = ["mm_init", "mm_step", "mm_add_probe", "mm_probe", "mm_get_field", "mm_set_field",
+EXPORTED = ["mm_init", "mm_step", "mm_add_probe", "mm_add_hard_source", "mm_add_surface_current",
+            "mm_probe", "mm_get_field", "mm_set_field",
             "mm_stats", "mm_sync", "mm_info", "mm_layout", "mm_adjoint_enable", "mm_adjoint", "mm_profile",
             "mm_profile_read", "mm_last_error", "mm_destroy"]
 
@@ -39,6 +40,19 @@ class mm_bias(C.Structure):
 class mm_source(C.Structure):
     _fields_ = [("comp", C.c_int32), ("profile", _dptr), ("f0", C.c_double),
                 ("Tp", C.c_double), ("t0", C.c_double)]
+
+
+class mm_hard_source(C.Structure):
+    _fields_ = [("field", C.c_int32), ("profile", _dptr), ("f0", C.c_double),
+                ("Tp", C.c_double), ("t0", C.c_double)]
+
+
+class mm_surface_current(C.Structure):
+    _fields_ = [("axis", C.c_int32), ("side", C.c_int32), ("comp", C.c_int32), ("profile", _dptr),
+                ("f0", C.c_double), ("Tp", C.c_double), ("t0", C.c_double)]
+
+
+MM_MAX_HARD = 8
 
 
 class mm_pml(C.Structure):
@@ -81,6 +95,10 @@ def load(path: str = LIB_PATH):
     lib.mm_step.restype = C.c_int
     lib.mm_add_probe.argtypes = [P, C.POINTER(mm_probe_desc), C.POINTER(C.c_int32)]
     lib.mm_add_probe.restype = C.c_int
+    lib.mm_add_hard_source.argtypes = [P, C.POINTER(mm_hard_source)]
+    lib.mm_add_hard_source.restype = C.c_int
+    lib.mm_add_surface_current.argtypes = [P, C.POINTER(mm_surface_current)]
+    lib.mm_add_surface_current.restype = C.c_int
     lib.mm_probe.argtypes = [P, C.c_int32, _dptr, C.c_size_t, C.POINTER(C.c_size_t), _dptr]
     lib.mm_probe.restype = C.c_int
     lib.mm_get_field.argtypes = [P, C.c_int32, _dptr]

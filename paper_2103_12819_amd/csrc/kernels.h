@@ -1186,4 +1186,34 @@ __global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, Lag<T> L, 
   }
 }
 
+// Hard source (Sec. 3.2): after an update of one E or H component, its
+// entries in the box [lo, lo + n) of staggered indices take prof * g (the
+// profile dense over the box, x fastest).  Entries pinned by a PEC wall
+// (tangential E, normal H) keep their zero.  One thread per box entry.
+struct Hard {
+  const double* prof;
+  int lo[3], n[3];
+  int comp;               // 0-2: E component, 3-5: H family + 3
+  double g;               // g at the level the update ends at
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void hard_set(Geo g, T* f, Hard s) {
+  const long long nb = (long long)s.n[0] * s.n[1] * s.n[2];
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb) return;
+  const int bi = (int)(t % s.n[0]);
+  const long long r = t / s.n[0];
+  const int p[3] = {s.lo[0] + bi, s.lo[1] + (int)(r % s.n[1]), s.lo[2] + (int)(r / s.n[1])};
+  const int n3[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < 3; ++a) {
+    if ((g.per >> a) & 1) continue;
+    // E_c is pinned on the walls normal to its other two axes, H_f on the
+    // walls normal to f
+    const bool wall_axis = s.comp < 3 ? a != s.comp : a == s.comp - 3;
+    if (wall_axis && (p[a] == 0 || p[a] == n3[a])) return;
+  }
+  f[at(g, p[0], p[1], p[2])] = (T)(s.prof[t] * s.g);
+}
+
 }  // namespace mmk

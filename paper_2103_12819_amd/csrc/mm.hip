@@ -45,6 +45,14 @@ struct AdjWork;
 
 }  // namespace
 
+// A hard source (Sec. 3.2): its profile dense over the box lo + [0, n).
+struct HardSrc {
+  int field;              // 0-2: E component, 3-5: H family + 3
+  int lo[3], n[3];
+  double* d_prof;
+  double f0, Tp, t0;
+};
+
 struct mm_ctx {
   // geometry
   int nx, ny, nz, per;
@@ -107,6 +115,9 @@ struct mm_ctx {
   int src_lo[3], src_hi[3];
   double* d_src_prof;
   double f0, Tp, t0;
+
+  // hard sources and surface currents (surface currents become hard H sources)
+  std::vector<HardSrc> hard;
 
   // probes
   std::vector<ProbeRec> probes;
@@ -523,8 +534,33 @@ int iterations_to_enqueue(const mm_ctx* c) {
 
 // One H-M sub-step.  near_only: the Faraday half step runs on the near
 // tiles only (the far tiles take it inside the fused pass of h_far).
+// Hard sources on E (e_field) or H, value g(t).
 template <typename T>
-mm_status substep(mm_ctx* c, bool near_only = false) {
+mm_status apply_hard(mm_ctx* c, bool e_field, double t) {
+  for (const HardSrc& hs : c->hard) {
+    if ((hs.field < 3) != e_field) continue;
+    mmk::Hard k;
+    k.prof = hs.d_prof;
+    for (int a = 0; a < 3; ++a) {
+      k.lo[a] = hs.lo[a];
+      k.n[a] = hs.n[a];
+    }
+    k.comp = hs.field;
+    k.g = waveform(t, hs.f0, hs.Tp, hs.t0);
+    T* f = (T*)(hs.field < 3 ? c->E[hs.field] : c->H[hs.field - 3]);
+    const long long nb = (long long)hs.n[0] * hs.n[1] * hs.n[2];
+    hipLaunchKernelGGL((mmk::hard_set<T>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, c->stream,
+                       make_geo(c), f, k);
+  }
+  HIPCHECK(c, hipGetLastError());
+  return MM_OK;
+}
+
+// One H-M sub-step (Step 1, or Step 3 when step3).  near_only: the Faraday
+// half step runs on the near tiles only (the far tiles take it inside the
+// fused pass of h_far).
+template <typename T>
+mm_status substep(mm_ctx* c, bool near_only = false, bool step3 = false) {
   Geo g = make_geo(c);
   mmk::Fields<T> F = make_fields<T>(c);
   const double h = 0.5 * c->dt;
@@ -574,6 +610,10 @@ mm_status substep(mm_ctx* c, bool near_only = false) {
                          (const T*)c->E[2], (const T*)c->mu, (T)hmu0, (T)h, tl, P);
   }
   HIPCHECK(c, hipGetLastError());
+  if (!c->hard.empty()) {
+    mm_status hs = apply_hard<T>(c, false, ((double)c->step + (step3 ? 1.0 : 0.5)) * c->dt);
+    if (hs) return hs;
+  }
   if (c->nmag > 0) {
     mmk::Mag m = make_mag(c);
     const int R = iterations_to_enqueue(c);
@@ -649,6 +689,7 @@ mm_status e_step(mm_ctx* c) {
                          (const T*)c->H[2], (const T*)c->eps, (const T*)c->sig, (T)c->dt, src, tp, P);
   }
   HIPCHECK(c, hipGetLastError());
+  if (!c->hard.empty()) return apply_hard<T>(c, true, ((double)c->step + 1.0) * c->dt);
   return MM_OK;
 }
 
@@ -704,11 +745,11 @@ mm_status record_probes(mm_ctx* c, bool lagged = false) {
 
 template <typename T>
 mm_status one_step(mm_ctx* c) {
-  mm_status s = substep<T>(c);  // Step 1
+  mm_status s = substep<T>(c);              // Step 1
   if (s) return s;
-  s = e_step<T>(c);             // Step 2
+  s = e_step<T>(c);                         // Step 2
   if (s) return s;
-  s = substep<T>(c);            // Step 3
+  s = substep<T>(c, false, true);           // Step 3
   if (s) return s;
   s = record_probes<T>(c);
   if (s) return s;
@@ -735,7 +776,7 @@ mm_status run_steps(mm_ctx* c, int64_t n) {
     const bool end = q == n - 1 || (c->ckpt_every > 0 && (c->step + 1) % c->ckpt_every == 0);
     if ((s = substep<T>(c, lagging))) return s;     // Step 1
     if ((s = e_step<T>(c))) return s;               // Step 2
-    if ((s = substep<T>(c, !end))) return s;        // Step 3
+    if ((s = substep<T>(c, !end, true))) return s;  // Step 3
     if ((s = record_probes<T>(c, !end))) return s;
     if (!end && (s = h_far<T>(c))) return s;
     lagging = !end;
@@ -907,6 +948,17 @@ mm_status build_tiles(mm_ctx* c) {
             else if (q[a] < 0 || q[a] >= n3[a]) ok = false;
           }
           if (ok) near[(q[0] / 64) + (size_t)c->tgx * ((q[1] / 4) + (size_t)c->tgy * (q[2] / c->tkc))] = 1;
+        }
+  }
+  // tiles holding a hard H source's faces take every half step on their own
+  for (const HardSrc& hs : c->hard) {
+    if (hs.field < 3) continue;
+    for (int k = hs.lo[2]; k < hs.lo[2] + hs.n[2]; ++k)
+      for (int j = hs.lo[1]; j < hs.lo[1] + hs.n[1]; ++j)
+        for (int i = hs.lo[0]; i < hs.lo[0] + hs.n[0]; ++i) {
+          // a face index along its normal runs to n (the wall); clip to the last cell
+          const int q0 = std::min(i, n3[0] - 1), q1 = std::min(j, n3[1] - 1), q2 = std::min(k, n3[2] - 1);
+          near[(q0 / 64) + (size_t)c->tgx * ((q1 / 4) + (size_t)c->tgy * (q2 / c->tkc))] = 1;
         }
   }
   // tiles holding layer entries: a cell within one cell of a layer
@@ -1398,6 +1450,132 @@ mm_status mm_step(mm_ctx* c, int64_t n) {
   return c->prec == MM_FP32 ? run_steps<float>(c, n) : run_steps<double>(c, n);
 }
 
+namespace {
+
+// Register a hard source on component `field` (0-5) from a host profile on
+// its staggered extent; see mm_add_hard_source for the conditions.
+mm_status add_hard(mm_ctx* c, int field, const double* profile, double f0, double Tp, double t0) {
+  if (c->step > 0 || c->substep > 0) return fail(c, MM_ESTATE, "hard sources must be added before the first step");
+  if (c->ckpt_every > 0) return fail(c, MM_EINVAL, "the adjoint does not cover hard sources");
+  if (field < 0 || field > 5 || !profile) return fail(c, MM_EINVAL, "bad hard source (field %d)", field);
+  if (!(Tp > 0) || !std::isfinite(f0) || !std::isfinite(t0)) return fail(c, MM_EINVAL, "bad hard source pulse");
+  if ((int)c->hard.size() >= MM_MAX_HARD) return fail(c, MM_EINVAL, "at most %d hard sources", MM_MAX_HARD);
+  int ext[3];
+  field_extent(c, field, ext);
+  auto prof_at = [&](int i, int j, int k) {
+    return profile[(size_t)i + (size_t)ext[0] * ((size_t)j + (size_t)ext[1] * k)];
+  };
+  int lo[3] = {ext[0], ext[1], ext[2]}, hi[3] = {0, 0, 0};
+  bool any = false;
+  for (int k = 0; k < ext[2]; ++k)
+    for (int j = 0; j < ext[1]; ++j)
+      for (int i = 0; i < ext[0]; ++i) {
+        const double v = prof_at(i, j, k);
+        if (!std::isfinite(v)) return fail(c, MM_EINVAL, "non-finite hard source profile");
+        if (v == 0.0 || !entry_interior(c, field, i, j, k)) continue;
+        any = true;
+        const int p[3] = {i, j, k};
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = std::min(lo[a], p[a]);
+          hi[a] = std::max(hi[a], p[a] + 1);
+        }
+      }
+  if (!any) return fail(c, MM_EINVAL, "a hard source needs a nonzero interior profile entry");
+  if (field >= 3) {
+    const int f = field - 3;
+    const int t0f = f == 0 ? 0 : (f == 1 ? c->off1 : c->off2);
+    const int t1f = f == 0 ? c->off1 : (f == 1 ? c->off2 : c->nmag);
+    for (int t = t0f; t < t1f; ++t) {
+      const size_t pi = (size_t)c->h_idx[t];
+      const int k = (int)(pi / ((size_t)c->px * c->py));
+      const size_t rr = pi - (size_t)k * c->px * c->py;
+      const int j = (int)(rr / c->px), i = (int)(rr % c->px);
+      if (i >= lo[0] && i < hi[0] && j >= lo[1] && j < hi[1] && k >= lo[2] && k < hi[2])
+        return fail(c, MM_EINVAL, "a hard H source may not hold evolving magnetic faces");
+    }
+  }
+  if (c->has_pml) {
+    const int n3[3] = {c->nx, c->ny, c->nz};
+    for (int a = 0; a < 3; ++a) {
+      const int lt = c->pml_cells[2 * a], ht = c->pml_cells[2 * a + 1];
+      // positions in cells: cell centres where the component is cell-centred
+      const bool cell_axis = field < 3 ? a == field : a != field - 3;
+      for (int q = lo[a]; q < hi[a]; ++q) {
+        const double pos = q + (cell_axis ? 0.5 : 0.0);
+        if ((lt > 0 && pos < lt) || (ht > 0 && pos > n3[a] - ht))
+          return fail(c, MM_EINVAL, "a hard source may not reach into an open-boundary layer");
+      }
+    }
+  }
+  HardSrc hs;
+  hs.field = field;
+  for (int a = 0; a < 3; ++a) {
+    hs.lo[a] = lo[a];
+    hs.n[a] = hi[a] - lo[a];
+  }
+  hs.f0 = f0;
+  hs.Tp = Tp;
+  hs.t0 = t0;
+  const size_t bx = hs.n[0], by = hs.n[1], bz = hs.n[2];
+  std::vector<double> box(bx * by * bz, 0.0);
+  for (size_t k = 0; k < bz; ++k)
+    for (size_t j = 0; j < by; ++j)
+      for (size_t i = 0; i < bx; ++i) {
+        const int gi = lo[0] + (int)i, gj = lo[1] + (int)j, gk = lo[2] + (int)k;
+        if (entry_interior(c, field, gi, gj, gk)) box[i + bx * (j + by * k)] = prof_at(gi, gj, gk);
+      }
+  hs.d_prof = (double*)dalloc(c, box.size() * sizeof(double));
+  if (!hs.d_prof) return fail(c, MM_ENOMEM, "hard source allocation failed");
+  HIPCHECK(c, hipMemcpy(hs.d_prof, box.data(), box.size() * sizeof(double), hipMemcpyHostToDevice));
+  c->hard.push_back(hs);
+  if (field >= 3) {
+    // the source's tiles leave the fused far pass: rebuild the tile lists
+    void* old[5] = {c->d_tl_all, c->d_tl_near, c->d_tl_far, c->d_far, c->d_tl_pml};
+    for (void* q : old)
+      if (q) dfree(c, q);
+    mm_status ts = build_tiles(c);
+    if (ts) return ts;
+  }
+  return MM_OK;
+}
+
+}  // namespace
+
+mm_status mm_add_hard_source(mm_ctx* c, const mm_hard_source* s) {
+  if (!c || !s) return MM_EINVAL;
+  return add_hard(c, s->field, s->profile, s->f0, s->Tp, s->t0);
+}
+
+mm_status mm_add_surface_current(mm_ctx* c, const mm_surface_current* s) {
+  if (!c || !s) return MM_EINVAL;
+  const int axis = s->axis, comp = s->comp, side = s->side;
+  if (axis < 0 || axis > 2 || comp < 0 || comp > 2 || comp == axis || (side != 0 && side != 1) || !s->profile)
+    return fail(c, MM_EINVAL, "bad surface current (axis %d, side %d, comp %d)", axis, side, comp);
+  if (c->per >> axis & 1) return fail(c, MM_EINVAL, "a surface current needs a PEC wall (axis %d is periodic)", axis);
+  const int h = 3 - axis - comp;
+  // H_t = J_s x n with n = +e_axis at the low wall and -e_axis at the high
+  // wall: H_h = J * eps(comp, axis, h) * (side ? -1 : +1)
+  const int eps = ((comp + 1) % 3 == axis) ? 1 : -1;
+  const double sign = side ? -eps : eps;
+  int je[3], he[3];
+  field_extent(c, comp, je);
+  field_extent(c, 3 + h, he);
+  std::vector<double> H((size_t)he[0] * he[1] * he[2], 0.0);
+  const int wall = side ? ncell(c, axis) : 0;       // the wall's node index along axis
+  const int first = side ? ncell(c, axis) - 1 : 0;  // the cell beside it
+  for (int k = 0; k < je[2]; ++k)
+    for (int j = 0; j < je[1]; ++j)
+      for (int i = 0; i < je[0]; ++i) {
+        const int p[3] = {i, j, k};
+        if (p[axis] != wall) continue;
+        int q[3] = {i, j, k};
+        q[axis] = first;
+        const double v = s->profile[(size_t)i + (size_t)je[0] * ((size_t)j + (size_t)je[1] * k)];
+        H[(size_t)q[0] + (size_t)he[0] * ((size_t)q[1] + (size_t)he[1] * q[2])] = sign * v;
+      }
+  return add_hard(c, 3 + h, H.data(), s->f0, s->Tp, s->t0);
+}
+
 mm_status mm_add_probe(mm_ctx* c, const mm_probe_desc* d, int32_t* id) {
   if (!c || !d) return MM_EINVAL;
   if (c->step > 0 || c->probes_frozen) return fail(c, MM_ESTATE, "probes must be added before the first step");
@@ -1663,6 +1841,7 @@ mm_status mm_layout(const mm_ctx* c, int64_t out[8]) {
 
 mm_status mm_adjoint_enable(mm_ctx* c, int32_t checkpoint_every, int32_t inner_every) {
   if (!c) return MM_EINVAL;
+  if (!c->hard.empty()) return fail(c, MM_EINVAL, "the adjoint does not cover hard sources");
   if (checkpoint_every < 1) return fail(c, MM_EINVAL, "checkpoint_every must be >= 1");
   if (inner_every < 0 || inner_every > checkpoint_every)
     return fail(c, MM_EINVAL, "inner_every must be in [0, checkpoint_every]");

@@ -35,6 +35,42 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+STRUCTS = ("mm_grid", "mm_materials", "mm_bias", "mm_source", "mm_hard_source", "mm_surface_current",
+           "mm_pml", "mm_options", "mm_probe_desc")
+
+
+def test_ctypes_mirror_matches_the_c_compiler(tmp_path):
+    """Size and every field offset of each struct, as gcc lays out the
+    header, against the ctypes mirror; and MM_MAX_HARD."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mm.h"', 'int main(void) {']
+    for st in STRUCTS:
+        lines.append(f'  printf("{st} size %zu\\n", sizeof({st}));')
+        for name, _ in getattr(N, st)._fields_:
+            lines.append(f'  printf("{st} {name} %zu\\n", offsetof({st}, {name}));')
+    lines.append('  printf("MM_MAX_HARD %d\\n", MM_MAX_HARD);')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, v = line.split() if len(line.split()) == 3 else (line.split()[0], "", line.split()[1])
+            got[(a, b)] = int(v)
+    for st in STRUCTS:
+        cls = getattr(N, st)
+        assert got[(st, "size")] == C.sizeof(cls), st
+        for name, _ in cls._fields_:
+            assert got[(st, name)] == getattr(cls, name).offset, (st, name)
+    assert got[("MM_MAX_HARD", "")] == N.MM_MAX_HARD
+
+
 def test_struct_layouts_match_the_header():
     # sizes on x86-64 (LP64): int32 x6 + padding + doubles / pointers
     assert C.sizeof(N.mm_grid) == 48
@@ -43,6 +79,8 @@ def test_struct_layouts_match_the_header():
     assert C.sizeof(N.mm_source) == 40
     assert C.sizeof(N.mm_options) == 72
     assert C.sizeof(N.mm_pml) == 40
+    assert C.sizeof(N.mm_hard_source) == 40
+    assert C.sizeof(N.mm_surface_current) == 48
     assert C.sizeof(N.mm_probe_desc) == 20
 
 
@@ -99,5 +137,7 @@ def test_null_pointers_are_rejected():
     lib = _lib()
     assert lib.mm_init(None, None, 1.0, None, None, None, None) == N.MM_EINVAL
     assert lib.mm_step(None, 1) == N.MM_EINVAL
+    assert lib.mm_add_hard_source(None, None) == N.MM_EINVAL
+    assert lib.mm_add_surface_current(None, None) == N.MM_EINVAL
     assert lib.mm_sync(None) == N.MM_EINVAL
     lib.mm_destroy(None)

@@ -521,15 +521,16 @@ int kchunk_for(const mm_ctx* c, dim3& grid) {
   return kc;
 }
 
-// Number of iterations to enqueue as ordinary launches: one more than the
-// largest count seen in the last 64 sub-steps (read from pinned memory the
-// device writes; stale values are harmless because hm_finish completes any
-// iterations that were not enqueued).
+// Number of iterations to enqueue as ordinary launches: the largest count
+// seen in the last 64 sub-steps (read from pinned memory the device writes;
+// stale values are harmless because hm_finish completes any iterations that
+// were not enqueued).  hm_finish also evaluates the stopping rule after the
+// last enqueued one, so no launch is spent only on finding that it fired.
 int iterations_to_enqueue(const mm_ctx* c) {
   if (c->fixed_iter > 0) return c->fixed_iter;
   int mx = 1;
   for (int q = 0; q < 64; ++q) mx = std::max(mx, (int)((volatile int*)c->h_ring)[q]);
-  return std::max(1, std::min(std::min(mx + 1, 32), c->max_iter));
+  return std::max(1, std::min(std::min(mx, 32), c->max_iter));
 }
 
 // One H-M sub-step.  near_only: the Faraday half step runs on the near

@@ -567,6 +567,8 @@ struct Mag {
   const double* Ms;          // face Ms
   const double* kap;         // mu0 * gamma_f * dt / 4 (signed gamma)
   const double* aoms;        // alpha_f / Ms_f
+  const unsigned char* fid;  // or null: per face an id into ftab, which holds
+  const double* ftab;        // (Ms, kap, aoms) per id (the same values, 1 byte per face)
   double* M[3];              // current iterate (components x, y, z)
   double* b[3];              // b of eq:llg_tra6 (signed-gamma form), per sub-step
   double* d[3];              // (alpha/Ms) M^s, per sub-step
@@ -581,6 +583,21 @@ __device__ __forceinline__ void log_iterate(const Mag& m, int r, int t, double v
   if (!m.hlog) return;
   if (r <= m.hlog_cap) m.hlog[(size_t)(r - 1) * m.n + t] = v;
   else atomicOr(err, 8);
+}
+
+// The face constants of evolving face t: from the per-face arrays, or by the
+// face's material id from the table.
+__device__ __forceinline__ void face_consts(const Mag& m, int t, double& Ms, double& kap, double& aoms) {
+  if (m.fid) {
+    const double* e = m.ftab + 3 * (int)m.fid[t];
+    Ms = e[0];
+    kap = e[1];
+    aoms = e[2];
+  } else {
+    Ms = m.Ms[t];
+    kap = m.kap[t];
+    aoms = m.aoms[t];
+  }
 }
 
 __device__ __forceinline__ void face_ijk(const Geo& g, int c, int& i, int& j, int& k) {
@@ -814,7 +831,9 @@ __device__ __forceinline__ unsigned long long iterate_faces(const Geo& g, const 
     const int f = face_family(m, t);
     const int c = m.idx[t];
     const unsigned mask = m.nbm[t];
-    const double Ms = m.Ms[t], kap = m.kap[t], qf = m.q[t];
+    double Ms, kap, aoms_unused;
+    face_consts(m, t, Ms, kap, aoms_unused);
+    const double qf = m.q[t];
     const double d[3] = {m.d[0][t], m.d[1][t], m.d[2][t]};
     const double b[3] = {m.b[0][t], m.b[1][t], m.b[2][t]};
     const double mo[3] = {m.M[0][t], m.M[1][t], m.M[2][t]};
@@ -867,7 +886,8 @@ __global__ __launch_bounds__(MM_MAG_THREADS) void hm_pre(Geo g, Fields<T> F, Mag
     // batch 1: everything indexed by the face number
     const int f = face_family(m, t);
     const int c = m.idx[t];
-    const double Ms = m.Ms[t], kap = m.kap[t], aoms = m.aoms[t];
+    double Ms, kap, aoms;
+    face_consts(m, t, Ms, kap, aoms);
     const double ms[3] = {m.M[0][t], m.M[1][t], m.M[2][t]};
     __builtin_amdgcn_sched_barrier(0);
     // batch 2: curl E and H^s around the face

@@ -8,11 +8,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <string>
 #include <unordered_map>
 #include <unordered_set>
@@ -92,6 +94,9 @@ struct mm_ctx {
   std::vector<int> h_fam;
   int* d_idx;
   double *d_Ms, *d_kap, *d_aoms;
+  unsigned char* d_fid;       // per evolving face: id of its (Ms, kap, aoms) in d_ftab, or null
+  double* d_ftab;             // when at most 256 distinct triples
+  int nfmat;
   double* d_M[3];
   double *d_b[3], *d_d[3], *d_q;
   unsigned char* d_nbm;       // neighbour masks of the evolving faces
@@ -463,6 +468,8 @@ mmk::Mag make_mag(const mm_ctx* c) {
   m.Ms = c->d_Ms;
   m.kap = c->d_kap;
   m.aoms = c->d_aoms;
+  m.fid = c->d_fid;
+  m.ftab = c->d_ftab;
   for (int a = 0; a < 3; ++a) {
     m.M[a] = c->d_M[a];
     m.b[a] = c->d_b[a];
@@ -1247,6 +1254,39 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
     HIPCHECK(c, hipMemcpy(c->d_aoms, hv[2].data(), ntot * sizeof(double), hipMemcpyHostToDevice));
     for (int a = 0; a < 3; ++a)
       HIPCHECK(c, hipMemcpy(c->d_M[a], hv[3 + a].data(), ntot * sizeof(double), hipMemcpyHostToDevice));
+    // face materials: the distinct (Ms, kap, aoms) triples of the evolving
+    // faces (bit-exact), a byte id per face when there are at most 256
+    c->d_fid = nullptr;
+    c->d_ftab = nullptr;
+    c->nfmat = 0;
+    if (c->nmag > 0) {
+      std::map<std::array<uint64_t, 3>, int> ids;
+      std::vector<unsigned char> fid(c->nmag);
+      std::vector<double> tab;
+      bool fits = true;
+      for (size_t t = 0; t < (size_t)c->nmag && fits; ++t) {
+        std::array<uint64_t, 3> key;
+        for (int v = 0; v < 3; ++v) std::memcpy(&key[v], &hv[v][t], sizeof(double));
+        auto it = ids.find(key);
+        if (it == ids.end()) {
+          if (ids.size() == 256) {
+            fits = false;
+            break;
+          }
+          it = ids.emplace(key, (int)ids.size()).first;
+          for (int v = 0; v < 3; ++v) tab.push_back(hv[v][t]);
+        }
+        fid[t] = (unsigned char)it->second;
+      }
+      if (fits) {
+        c->nfmat = (int)ids.size();
+        c->d_fid = (unsigned char*)dalloc(c, c->nmag);
+        c->d_ftab = (double*)dalloc(c, tab.size() * sizeof(double));
+        if (!c->d_fid || !c->d_ftab) return fail(c, MM_ENOMEM, "face-material allocation failed");
+        HIPCHECK(c, hipMemcpy(c->d_fid, fid.data(), c->nmag, hipMemcpyHostToDevice));
+        HIPCHECK(c, hipMemcpy(c->d_ftab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+      }
+    }
   }
   c->nres = std::max(c->max_iter, c->fixed_iter) + 2;
   c->step_blocks = c->fin_blocks = 1;

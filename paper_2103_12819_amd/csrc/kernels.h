@@ -541,7 +541,8 @@ template <typename T>
 struct Fields {
   T* E[3];
   T* H[3];
-  T* A[3];   // shadow H on magnetic faces (ping-pong partner of H during the iteration)
+  T* A[3];   // shadow H on magnetic faces: iterates r = 1, 4, 7, ...
+  T* B[3];   // second shadow: iterates r = 2, 5, 8, ...; r = 3, 6, ... go to H
 };
 
 // Three component pointers held in registers.  A per-thread component index
@@ -559,6 +560,17 @@ struct Tri {
 template <typename T>
 __device__ __forceinline__ Tri<T> tri(T* const (&a)[3]) {
   return Tri<T>{a[0], a[1], a[2]};
+}
+
+// Where iteration r writes H on the evolving faces.  The iterates rotate
+// through A, B and H: iteration r reads r-1 from the previous buffer while
+// no thread reads the one it writes (the faces of H it writes are read by
+// nobody in that iteration: other faces' reads of evolving neighbours go to
+// the previous iterate), and the usual count of 3 ends in H itself.
+template <typename T>
+__device__ __forceinline__ Tri<T> iter_buf(const Fields<T>& F, int r) {
+  const int q = r % 3;
+  return q == 1 ? tri(F.A) : (q == 2 ? tri(F.B) : tri(F.H));
 }
 
 struct Mag {
@@ -948,7 +960,7 @@ __global__ __launch_bounds__(MM_MAG_THREADS) void hm_pre(Geo g, Fields<T> F, Mag
 // Iteration r >= 2 as an ordinary launch.  Every thread evaluates the
 // stopping rule on iteration r-1's residual (the same value everywhere) and
 // the whole grid returns at once when it fires; block 0 then records the
-// final count.  H^{(r)} goes to H for even r and to A for odd r.
+// final count.  H^{(r)} goes where iter_buf puts it.
 template <typename T>
 __global__ __launch_bounds__(MM_MAG_THREADS) void hm_step(Geo g, Fields<T> F, Mag m, double H0x, double H0y,
                                               double H0z, Ctl C, int r, int* err) {
@@ -958,8 +970,8 @@ __global__ __launch_bounds__(MM_MAG_THREADS) void hm_step(Geo g, Fields<T> F, Ma
     if (blockIdx.x == 0 && threadIdx.x == 0) C.cur[0] = (unsigned long long)(r - 1);
     return;
   }
-  const Tri<T> prev = (r & 1) ? tri(F.H) : tri(F.A);
-  const Tri<T> out = (r & 1) ? tri(F.A) : tri(F.H);
+  const Tri<T> prev = iter_buf(F, r - 1);
+  const Tri<T> out = iter_buf(F, r);
   const unsigned long long lb = iterate_faces(g, m, F, prev, out, blockIdx.x * blockDim.x + threadIdx.x,
                                               gridDim.x * blockDim.x, H0x, H0y, H0z, r, err);
   publish_residual(C, r, lb);
@@ -1008,8 +1020,8 @@ __global__ __launch_bounds__(256) void hm_finish(Geo g, Fields<T> F, Mag m, doub
   int r = r_next;
   for (;;) {
     if (stop_rule(C, r - 1, residual_bits(C, r - 1), bad)) break;
-    const Tri<T> prev = (r & 1) ? tri(F.H) : tri(F.A);
-    const Tri<T> out = (r & 1) ? tri(F.A) : tri(F.H);
+    const Tri<T> prev = iter_buf(F, r - 1);
+    const Tri<T> out = iter_buf(F, r);
     const unsigned long long lb = iterate_faces(g, m, F, prev, out, tid, nth, H0x, H0y, H0z, r, err);
     publish_residual(C, r, lb);
     if (!grid_barrier(bar)) {
@@ -1022,20 +1034,22 @@ __global__ __launch_bounds__(256) void hm_finish(Geo g, Fields<T> F, Mag m, doub
   if (blockIdx.x == 0 && threadIdx.x == 0) C.cur[0] = (unsigned long long)(r - 1);
 }
 
-// End of a sub-step: bring the final magnetic H into H when it sits in A
-// (odd count), record the count and the sticky flags, and clear the other
-// sub-step's final count.
+// End of a sub-step: bring the final magnetic H into H when it sits in A or
+// B (a count that is not a multiple of 3), record the count and the sticky
+// flags, and clear the other sub-step's final count.
 template <typename T>
 __global__ __launch_bounds__(MM_MAG_THREADS) void hm_commit(Fields<T> F, Mag m, Ctl C, int* iters_out, int* ring,
                                                 int* err) {
   const int rfin = (int)load_u64(&C.cur[0]);
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (rfin & 1)
+  if (rfin % 3 != 0) {
+    const Tri<T> src = iter_buf(F, rfin);
     for (int t = tid; t < m.n; t += gridDim.x * blockDim.x) {
       const int f = face_family(m, t);
       const int c = m.idx[t];
-      tri(F.H)(f)[c] = tri(F.A)(f)[c];
+      tri(F.H)(f)[c] = src(f)[c];
     }
+  }
   if (blockIdx.x == 0) {
     const unsigned long long bits = residual_bits(C, rfin);
     if (threadIdx.x == 0) {

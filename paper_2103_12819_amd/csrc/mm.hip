@@ -100,7 +100,8 @@ struct mm_ctx {
   double* d_M[3];
   double *d_b[3], *d_d[3], *d_q;
   unsigned char* d_nbm;       // neighbour masks of the evolving faces
-  void* A[3];                 // shadow H (ping-pong partner of H on magnetic faces)
+  void* A[3];                 // shadow H arrays: the H-M iterates rotate through A, B and H
+  void* B[3];
   unsigned long long* d_res;  // final iteration count of the two sub-step parities
   unsigned long long* d_part; // residual partials: 2 parities x nres iterations x step_blocks
   int nres;
@@ -458,6 +459,7 @@ mmk::Fields<T> make_fields(const mm_ctx* c) {
     F.E[a] = (T*)c->E[a];
     F.H[a] = (T*)c->H[a];
     F.A[a] = (T*)c->A[a];
+    F.B[a] = (T*)c->B[a];
   }
   return F;
 }
@@ -1211,8 +1213,10 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
       return fail(c, MM_ENOMEM, "magnetic-face allocation failed");
     for (int a = 0; a < 3; ++a) {
       c->A[a] = dalloc(c, c->nelem * c->esz);
-      if (!c->A[a]) return fail(c, MM_ENOMEM, "allocation of the shadow H failed");
+      c->B[a] = dalloc(c, c->nelem * c->esz);
+      if (!c->A[a] || !c->B[a]) return fail(c, MM_ENOMEM, "allocation of the shadow H failed");
       HIPCHECK(c, hipMemsetAsync(c->A[a], 0, c->nelem * c->esz, c->stream));
+      HIPCHECK(c, hipMemsetAsync(c->B[a], 0, c->nelem * c->esz, c->stream));
     }
     // neighbour masks: bit q set when transverse neighbour q (numbered as in
     // mmk::h_eff) is an evolving magnetic face

@@ -60,15 +60,17 @@ def measured_traffic(kernel, cells_per_launch):
 # two-half-step instantiation of h_bulk)
 _PMC_NAMES = (("e_update", "e_update<double"), ("h_far", "h_bulk<double, false, 2>"),
               ("h_bulk", "h_bulk<double, false, 1>"), ("hm_pre", "hm_pre<double"),
-              ("hm_step", "hm_step<double"), ("hm_commit", "hm_commit<double"),
-              ("probe_flux", "probe_flux<double"))
+              ("hm_step", "hm_step<double"), ("hm_finish", "hm_finish<double"),
+              ("hm_commit", "hm_commit<double"), ("probe_flux", "probe_flux<double"))
 
 
 def write_traffic_record(pmc_dir, workload="filter512"):
     """Turn the four rocprofv3 counter runs under `pmc_dir` (FETCH_SIZE and
-    WRITE_SIZE of `bench.py --start 0 --steps 3 --warmup 1 --no-cpu --no-fp32
-    --no-adjoint` and of `bench.py --calibrate-copy`) into the traffic record
-    and a markdown table; CPU only.  Counter values are KiB per dispatch."""
+    WRITE_SIZE of `bench.py --steps 3 --warmup 1 --no-cpu --no-fp32
+    --no-adjoint`, whose 600 set-up steps reach the part of the run where the
+    H-M iteration takes 3 iterations, and of `bench.py --calibrate-copy`) into
+    the traffic record and a markdown table; CPU only.  Counter values are
+    KiB per dispatch."""
     import sqlite3
 
     def per_kernel(db):
@@ -98,7 +100,7 @@ def write_traffic_record(pmc_dir, workload="filter512"):
     fetch, write = one("FETCH_SIZE", "bench"), one("WRITE_SIZE", "bench")
     rec = {"kernels_h_sha256": _kernels_h_sha256(),
            "workload": f"{cfg.name} {cfg.n[0]}x{cfg.n[1]}x{cfg.n[2]} fp64",
-           "command": "bench.py --start 0 --steps 3 --warmup 1 --no-cpu --no-fp32 --no-adjoint",
+           "command": "bench.py --steps 3 --warmup 1 --no-cpu --no-fp32 --no-adjoint",
            "fetch_scale": scale["FETCH_SIZE"], "write_scale": scale["WRITE_SIZE"], "kernels": {}}
     lines = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read GB | write GB | "
              "algorithmic GB | traffic / algorithmic |", "|---|---|---|---|---|---|---|---|"]

@@ -218,6 +218,17 @@ mm_status mm_get_field(mm_ctx *c, int32_t field, double *dst);
  * are forced to zero.  Allowed at any step boundary. */
 mm_status mm_set_field(mm_ctx *c, int32_t field, const double *src);
 
+/* Device-side access to E or H component `field` (0-5), in the storage
+ * precision (8-byte doubles, or 4-byte floats in MM_FP32; mm_info out[6]):
+ * `dst` / `src` is device memory on the context's device holding the
+ * component's staggered extent densely, x fastest (the host layout of
+ * mm_get_field).  Both are enqueued on the context's stream and return
+ * without waiting; the caller orders its own use of the buffer against that
+ * stream.  mm_set_field_device forces tangential E and normal H on PEC walls
+ * to zero, as mm_set_field does; allowed at any step boundary. */
+mm_status mm_get_field_device(mm_ctx *c, int32_t field, void *dst);
+mm_status mm_set_field_device(mm_ctx *c, int32_t field, const void *src);
+
 /* Iteration counts of the sub-steps done so far (two per step, in order)
  * into `iters` (up to cap; may be NULL); *n gets the total count.
  * Synchronises the stream and returns the sticky device condition. */

@@ -31,6 +31,14 @@ class MMError(RuntimeError):
         self.status = status
 
 
+class _nullctx:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        return False
+
+
 def _dp(a):
     if a is None:
         return None
@@ -198,6 +206,29 @@ class Sim:
         if a.shape != self.extent(fid):
             raise ValueError(f"{name}: expected shape {self.extent(fid)}, got {a.shape}")
         self._check(self._lib.mm_set_field(self._ctx, fid, _dp(a)))
+
+    def field_tensor(self, name):
+        """E or H component as a torch tensor on the device (storage precision,
+        host-layout shape), filled on the context's stream without a host copy."""
+        import torch
+        fid = FIELD_ID[name] if isinstance(name, str) else int(name)
+        if fid > 5:
+            raise ValueError("device access covers E and H components only")
+        dt = torch.float32 if self.precision == "fp32" else torch.float64
+        with torch.cuda.stream(torch.cuda.ExternalStream(self.stream)) if self.stream else _nullctx():
+            out = torch.empty(self.extent(fid), dtype=dt, device="cuda")
+        self._check(self._lib.mm_get_field_device(self._ctx, fid, C.c_void_p(out.data_ptr())))
+        return out
+
+    def set_field_tensor(self, name, t):
+        """Overwrite an E or H component from a contiguous device tensor of the
+        storage precision and host-layout shape (PEC-pinned entries -> 0)."""
+        import torch
+        fid = FIELD_ID[name] if isinstance(name, str) else int(name)
+        dt = torch.float32 if self.precision == "fp32" else torch.float64
+        if t.dtype != dt or tuple(t.shape) != self.extent(fid) or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous {dt} device tensor of shape {self.extent(fid)}")
+        self._check(self._lib.mm_set_field_device(self._ctx, fid, C.c_void_p(t.data_ptr())))
 
     def set_fields(self, E=None, H=None):
         if E is not None:

@@ -14,7 +14,7 @@ MM_BC_PEC, MM_BC_PERIODIC = 0, 1
 MM_FP64, MM_FP32 = 0, 1
 
 EXPORTED = ["mm_init", "mm_step", "mm_add_probe", "mm_add_hard_source", "mm_add_surface_current",
-            "mm_probe", "mm_get_field", "mm_set_field",
+            "mm_probe", "mm_get_field", "mm_set_field", "mm_get_field_device", "mm_set_field_device",
             "mm_stats", "mm_sync", "mm_info", "mm_layout", "mm_adjoint_enable", "mm_adjoint", "mm_profile",
             "mm_profile_read", "mm_last_error", "mm_destroy"]
 
@@ -104,6 +104,10 @@ def load(path: str = LIB_PATH):
     lib.mm_get_field.argtypes = [P, C.c_int32, _dptr]
     lib.mm_get_field.restype = C.c_int
     lib.mm_set_field.argtypes = [P, C.c_int32, _dptr]
+    lib.mm_get_field_device.argtypes = [P, C.c_int32, C.c_void_p]
+    lib.mm_get_field_device.restype = C.c_int
+    lib.mm_set_field_device.argtypes = [P, C.c_int32, C.c_void_p]
+    lib.mm_set_field_device.restype = C.c_int
     lib.mm_set_field.restype = C.c_int
     lib.mm_stats.argtypes = [P, C.POINTER(C.c_int32), C.c_size_t, C.POINTER(C.c_size_t)]
     lib.mm_stats.restype = C.c_int

@@ -1832,6 +1832,61 @@ mm_status mm_set_field(mm_ctx* c, int32_t field, const double* src) {
   return MM_OK;
 }
 
+namespace {
+
+// Copy between the padded device array of E/H component `field` and a dense
+// device buffer of its staggered extent (to_dense: padded -> dense).
+mm_status copy_dense(mm_ctx* c, int field, void* dense, bool to_dense) {
+  int ext[3];
+  field_extent(c, field, ext);
+  void* p = field < 3 ? c->E[field] : c->H[field - 3];
+  hipMemcpy3DParms q;
+  std::memset(&q, 0, sizeof q);
+  const hipPitchedPtr padded = make_hipPitchedPtr(p, (size_t)c->px * c->esz, (size_t)c->px, (size_t)c->py);
+  const hipPitchedPtr flat = make_hipPitchedPtr(dense, (size_t)ext[0] * c->esz, (size_t)ext[0], (size_t)ext[1]);
+  q.srcPtr = to_dense ? padded : flat;
+  q.dstPtr = to_dense ? flat : padded;
+  q.extent = make_hipExtent((size_t)ext[0] * c->esz, (size_t)ext[1], (size_t)ext[2]);
+  q.kind = hipMemcpyDeviceToDevice;
+  HIPCHECK(c, hipMemcpy3DAsync(&q, c->stream));
+  return MM_OK;
+}
+
+}  // namespace
+
+mm_status mm_get_field_device(mm_ctx* c, int32_t field, void* dst) {
+  if (!c || !dst) return MM_EINVAL;
+  if (field < 0 || field > 5) return fail(c, MM_EINVAL, "device access covers E and H components only");
+  return copy_dense(c, field, dst, true);
+}
+
+mm_status mm_set_field_device(mm_ctx* c, int32_t field, const void* src) {
+  if (!c || !src) return MM_EINVAL;
+  if (field < 0 || field > 5) return fail(c, MM_EINVAL, "only E and H components can be set");
+  mm_status s = copy_dense(c, field, const_cast<void*>(src), false);
+  if (s) return s;
+  // PEC walls: E_c is pinned where an index along a != c is 0 or n_a, H_f
+  // where its index along f is 0 or n_f
+  char* p = (char*)(field < 3 ? c->E[field] : c->H[field - 3]);
+  int ext[3];
+  field_extent(c, field, ext);
+  const size_t es = c->esz, row = (size_t)c->px * es, plane = row * c->py;
+  for (int a = 0; a < 3; ++a) {
+    const bool wall_axis = field < 3 ? a != field : a == field - 3;
+    if (!wall_axis || (c->per >> a & 1)) continue;
+    for (int v : {0, ncell(c, a)}) {
+      if (a == 2) {
+        HIPCHECK(c, hipMemsetAsync(p + (size_t)v * plane, 0, plane, c->stream));
+      } else if (a == 1) {
+        HIPCHECK(c, hipMemset2DAsync(p + (size_t)v * row, plane, 0, row, (size_t)ext[2], c->stream));
+      } else {
+        HIPCHECK(c, hipMemset2DAsync(p + (size_t)v * es, row, 0, es, (size_t)c->py * ext[2], c->stream));
+      }
+    }
+  }
+  return MM_OK;
+}
+
 mm_status mm_stats(mm_ctx* c, int32_t* iters, size_t cap, size_t* n) {
   if (!c) return MM_EINVAL;
   HIPCHECK(c, hipStreamSynchronize(c->stream));

@@ -530,20 +530,20 @@ int kchunk_for(const mm_ctx* c, dim3& grid) {
   return kc;
 }
 
-// Number of iterations to enqueue as ordinary launches: the largest count
-// seen in the last 64 sub-steps (read from pinned memory the device writes;
-// stale values are harmless because hm_finish completes any iterations that
-// were not enqueued).  hm_finish also evaluates the stopping rule after the
-// last enqueued one, so no launch is spent only on finding that it fired.
+// Number of iterations to enqueue as ordinary launches: one more than the
+// largest count seen in the last 64 sub-steps (read from pinned memory the
+// device writes; stale values are harmless because hm_finish completes any
+// iterations that were not enqueued).  The spare launch usually only finds
+// that the stopping rule has fired, at no measurable cost; when the count
+// rises by one it runs that iteration on the full grid instead of on
+// hm_finish's small co-resident one.
 int iterations_to_enqueue(const mm_ctx* c) {
   if (c->fixed_iter > 0) return c->fixed_iter;
   int mx = 1;
   for (int q = 0; q < 64; ++q) mx = std::max(mx, (int)((volatile int*)c->h_ring)[q]);
-  return std::max(1, std::min(std::min(mx, 32), c->max_iter));
+  return std::max(1, std::min(std::min(mx + 1, 32), c->max_iter));
 }
 
-// One H-M sub-step.  near_only: the Faraday half step runs on the near
-// tiles only (the far tiles take it inside the fused pass of h_far).
 // Hard sources on E (e_field) or H, value g(t).
 template <typename T>
 mm_status apply_hard(mm_ctx* c, bool e_field, double t) {

@@ -1,0 +1,120 @@
+"""The full 512 x 256 x 256 filter grid (33.5M cells) in the benchmark's launch
+configuration, checked against the oracle on sampled crops.
+
+The HIP path runs the benchmark's course: 600 set-up steps, 10 more, then a
+call of 2 steps (within a call the far tiles lag half a step and take the
+fused Faraday pass).  Before that last call the state (E, H, M) is read back;
+for each sampled point the oracle restarts from that state on a 64-cell crop
+around it and takes the same 2 steps with the iteration count the GPU used
+(3 per sub-step in this part of the run).  Within 2 steps a value depends
+only on its neighbourhood (per sub-step: the curl, one cell, and one cell per
+Jacobi iteration; one more for the E update), so a crop's centre, 24 cells
+away from any side the crop cuts through the grid, is exact; sides that lie
+on the grid's own walls need no margin.  Samples: the middle of ferrite bar
+A, the corners of both bars, the port plane, far tiles among the dielectric
+boxes, and the corner at the high walls.
+
+Bars: FP64 at 1e-12 (normwise, per group E, H, M over the crop centre); the
+FP32 bulk mode at 1e-5 (two steps of FP32 rounding from the same FP32 state).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Simulation
+from oracle.yee_llg import to_ijk
+from tests import parity_util as PU
+
+pytestmark = pytest.mark.gpu
+HALF, MARGIN, STEPS = 32, 24, 2
+SAMPLES = [(256, 16, 128), (384, 224, 160), (128, 32, 96), (8, 128, 128), (300, 128, 40), (500, 250, 250)]
+
+
+def _box(c, n):
+    lo = [max(0, c[a] - HALF) for a in range(3)]
+    hi = [min(n[a], c[a] + HALF) for a in range(3)]
+    return lo, hi
+
+
+def _crop(arr, lo, hi, stag):
+    """Host-layout [z][y][x] crop of a staggered array: `stag[a]` is 1 where the
+    array lives on nodes along axis a (one more entry)."""
+    return np.ascontiguousarray(arr[lo[2]:hi[2] + stag[2], lo[1]:hi[1] + stag[1], lo[0]:hi[0] + stag[0]])
+
+
+def _stag(field):
+    if field < 3:
+        return [0 if a == field else 1 for a in range(3)]
+    f = (field - 3) % 3 if field < 6 else (field - 6) // 3
+    return [1 if a == f else 0 for a in range(3)]
+
+
+def _centre(lo, hi, n, stag):
+    """Slices of the crop (host layout) that are exact: MARGIN from every side
+    the crop cuts through the grid."""
+    sl = []
+    for a in (2, 1, 0):
+        a0 = 0 if lo[a] == 0 else MARGIN
+        a1 = (hi[a] - lo[a] + stag[a]) - (0 if hi[a] == n[a] else MARGIN)
+        sl.append(slice(a0, a1))
+    return tuple(sl)
+
+
+def _run(precision, tol):
+    import paper_2103_12819_amd as mm
+    cfg = W.filter512(seed=0)
+    n = cfg.n
+    sim = mm.from_config(cfg, precision=precision, with_probes=False)
+    sim.step(600)
+    sim.step(10)
+    names = PU.E_H + PU.M_NAMES
+    fids = list(range(6)) + [W.FIELD_ID[nm] for nm in PU.M_NAMES]
+    boxes = [_box(c, n) for c in SAMPLES]
+
+    def crops():
+        out = [dict() for _ in SAMPLES]
+        for nm, fid in zip(names, fids):
+            full = sim.field(nm)
+            for q, (lo, hi) in enumerate(boxes):
+                out[q][nm] = _crop(full, lo, hi, _stag(fid))
+            del full
+        return out
+
+    before = crops()
+    n_sub = len(sim.stats())
+    sim.step(STEPS)
+    after = crops()
+    iters = sim.stats()[n_sub:]
+    sim.close()
+    assert list(iters) == [3] * (2 * STEPS), list(iters)
+    src = cfg.source
+    for q, (lo, hi) in enumerate(boxes):
+        nc = tuple(hi[a] - lo[a] for a in range(3))
+        cell = lambda a: np.ascontiguousarray(a[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]])  # noqa: E731
+        prof = _crop(src.profile, lo, hi, _stag(src.comp))
+        ref = Simulation(nc, cfg.d, cfg.dt, eps_r=cell(cfg.eps_r), sigma=cell(cfg.sigma), mu_r=cell(cfg.mu_r),
+                         Ms=cell(cfg.Ms), alpha=cell(cfg.alpha), gamma=cell(cfg.gamma), H0=cfg.H0,
+                         source=(src.comp, prof, src.f0, src.Tp, src.t0) if np.any(prof) else None,
+                         tol=cfg.tol, fixed_iter=3)
+        ref.set_fields([before[q][nm] for nm in PU.E_H[:3]], [before[q][nm] for nm in PU.E_H[3:]])
+        for f in range(3):
+            for c in range(3):
+                ref.M[f][c] = np.where(ref.mag[f], to_ijk(before[q]["M" + "xyz"[f] + "xyz"[c]]), 0.0)
+        ref.step_count = 610
+        ref.step(STEPS)
+        errs = {}
+        for grp, members in (("E", PU.E_H[:3]), ("H", PU.E_H[3:]), ("M", PU.M_NAMES)):
+            num = den = 0.0
+            for nm in members:
+                sl = _centre(lo, hi, n, _stag(W.FIELD_ID[nm]))
+                g, r = after[q][nm][sl], ref.field(nm)[sl]
+                num += float(np.sum((g - r) ** 2))
+                den += float(np.sum(r ** 2))
+            errs[grp] = np.sqrt(num / den) if den > 0 else np.sqrt(num)
+        print(SAMPLES[q], {k: f"{v:.2e}" for k, v in errs.items()})
+        assert errs["E"] <= tol and errs["H"] <= tol and errs["M"] <= tol, (SAMPLES[q], errs)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_filter512_sampled_crops_match_the_oracle(precision, tol):
+    _run(precision, tol)

@@ -6,13 +6,18 @@ call of 2 steps (within a call the far tiles lag half a step and take the
 fused Faraday pass).  Before that last call the state (E, H, M) is read back;
 for each sampled point the oracle restarts from that state on a 64-cell crop
 around it and takes the same 2 steps with the iteration count the GPU used
-(3 per sub-step in this part of the run).  Within 2 steps a value depends
+(3 per sub-step in this part of the run; the test asserts one count).  Within 2 steps a value depends
 only on its neighbourhood (per sub-step: the curl, one cell, and one cell per
 Jacobi iteration; one more for the E update), so a crop's centre, 24 cells
 away from any side the crop cuts through the grid, is exact; sides that lie
 on the grid's own walls need no margin.  Samples: the middle of ferrite bar
 A, the corners of both bars, the port plane, far tiles among the dielectric
 boxes, and the corner at the high walls.
+
+The 1024 x 512 x 512 grid (268M cells, three ferrite inclusions, FP32 bulk
+mode) is checked the same way after 450 steps; its iteration counts vary
+between sub-steps, so the 2-step window is the first one (of up to five)
+whose four sub-steps took the same count, which the oracle then uses.
 
 Bars: FP64 at 1e-12 (normwise, per group E, H, M over the crop centre); the
 FP32 bulk mode at 1e-5 (two steps of FP32 rounding from the same FP32 state).
@@ -28,6 +33,10 @@ from tests import parity_util as PU
 pytestmark = pytest.mark.gpu
 HALF, MARGIN, STEPS = 32, 24, 2
 SAMPLES = [(256, 16, 128), (384, 224, 160), (128, 32, 96), (8, 128, 128), (300, 128, 40), (500, 250, 250)]
+# (x, y, z): inside inclusion 1 and at its corner, the edge of inclusion 3,
+# the port plane, far tiles, the corner at the high walls
+SAMPLES_1024 = [(192, 416, 224), (255, 447, 255), (256, 400, 300), (16, 256, 256), (800, 100, 100),
+                (1020, 508, 508)]
 
 
 def _box(c, n):
@@ -60,19 +69,18 @@ def _centre(lo, hi, n, stag):
     return tuple(sl)
 
 
-def _run(precision, tol):
+def _run(cfg, samples, setup, precision, tol):
     import paper_2103_12819_amd as mm
-    cfg = W.filter512(seed=0)
     n = cfg.n
     sim = mm.from_config(cfg, precision=precision, with_probes=False)
-    sim.step(600)
-    sim.step(10)
+    for s_ in setup:
+        sim.step(s_)
     names = PU.E_H + PU.M_NAMES
     fids = list(range(6)) + [W.FIELD_ID[nm] for nm in PU.M_NAMES]
-    boxes = [_box(c, n) for c in SAMPLES]
+    boxes = [_box(c, n) for c in samples]
 
     def crops():
-        out = [dict() for _ in SAMPLES]
+        out = [dict() for _ in samples]
         for nm, fid in zip(names, fids):
             full = sim.field(nm)
             for q, (lo, hi) in enumerate(boxes):
@@ -80,13 +88,19 @@ def _run(precision, tol):
             del full
         return out
 
-    before = crops()
-    n_sub = len(sim.stats())
-    sim.step(STEPS)
     after = crops()
-    iters = sim.stats()[n_sub:]
+    for _attempt in range(5):
+        before = after
+        n_sub = len(sim.stats())
+        start = n_sub // 2
+        sim.step(STEPS)
+        after = crops()
+        iters = list(sim.stats()[n_sub:])
+        if len(set(iters)) == 1:
+            break
     sim.close()
-    assert list(iters) == [3] * (2 * STEPS), list(iters)
+    assert len(set(iters)) == 1, iters
+    count = iters[0]
     src = cfg.source
     for q, (lo, hi) in enumerate(boxes):
         nc = tuple(hi[a] - lo[a] for a in range(3))
@@ -95,12 +109,12 @@ def _run(precision, tol):
         ref = Simulation(nc, cfg.d, cfg.dt, eps_r=cell(cfg.eps_r), sigma=cell(cfg.sigma), mu_r=cell(cfg.mu_r),
                          Ms=cell(cfg.Ms), alpha=cell(cfg.alpha), gamma=cell(cfg.gamma), H0=cfg.H0,
                          source=(src.comp, prof, src.f0, src.Tp, src.t0) if np.any(prof) else None,
-                         tol=cfg.tol, fixed_iter=3)
+                         tol=cfg.tol, fixed_iter=count)
         ref.set_fields([before[q][nm] for nm in PU.E_H[:3]], [before[q][nm] for nm in PU.E_H[3:]])
         for f in range(3):
             for c in range(3):
                 ref.M[f][c] = np.where(ref.mag[f], to_ijk(before[q]["M" + "xyz"[f] + "xyz"[c]]), 0.0)
-        ref.step_count = 610
+        ref.step_count = start
         ref.step(STEPS)
         errs = {}
         for grp, members in (("E", PU.E_H[:3]), ("H", PU.E_H[3:]), ("M", PU.M_NAMES)):
@@ -111,10 +125,14 @@ def _run(precision, tol):
                 num += float(np.sum((g - r) ** 2))
                 den += float(np.sum(r ** 2))
             errs[grp] = np.sqrt(num / den) if den > 0 else np.sqrt(num)
-        print(SAMPLES[q], {k: f"{v:.2e}" for k, v in errs.items()})
-        assert errs["E"] <= tol and errs["H"] <= tol and errs["M"] <= tol, (SAMPLES[q], errs)
+        print(samples[q], "iterations", count, {k: f"{v:.2e}" for k, v in errs.items()})
+        assert errs["E"] <= tol and errs["H"] <= tol and errs["M"] <= tol, (samples[q], errs)
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_filter512_sampled_crops_match_the_oracle(precision, tol):
-    _run(precision, tol)
+    _run(W.filter512(seed=0), SAMPLES, (600, 10), precision, tol)
+
+
+def test_scale1024_fp32_sampled_crops_match_the_oracle():
+    _run(W.scale1024(seed=0), SAMPLES_1024, (450,), "fp32", 1e-5)

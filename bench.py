@@ -1,6 +1,7 @@
 """Throughput of the coupled Maxwell-LLG step on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--start S] [--workload filter512] [--no-cpu]
+    python bench.py --config-table     # oracle vs GPU on the paper-shaped grids
 
 A step is one full coupled time step (Step 1 H-M sub-step, Step 2 E update
 with the soft source, Step 3 H-M sub-step, probe sampling) on the
@@ -294,26 +295,77 @@ def run_scale(steps=500, ckpt=100, inner=10):
             "max_abs_grad_Ms": float(np.abs(gm).max())}
 
 
-def cpu_baseline(budget_s=15.0):
-    """The oracle on the 128x64x64 crop of the same grid, as many steps as fit
-    in the time budget (at least 2)."""
+def cpu_baseline(budget_s=15.0, cfg=None, label="the 128x64x64 crop of the filter grid", warm=True,
+                 max_steps=2000):
+    """The oracle on `cfg` (default: the 128x64x64 crop of the same grid), as
+    many steps as fit in the time budget (at least 2).  warm: one step
+    before the timing (allocation warm-up)."""
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     from oracle import from_config as oracle_from_config
-    cfg = W.filter_crop(seed=0, steps=1)
+    if cfg is None:
+        cfg = W.filter_crop(seed=0, steps=1)
     sim = oracle_from_config(cfg)
-    sim.step(1)              # first step outside the timing (allocation warm-up)
+    if warm:
+        sim.step(1)
     n = 0
     t0 = time.perf_counter()
     while True:
         sim.step(1)
         n += 1
         el = time.perf_counter() - t0
-        if (el > budget_s and n >= 2) or n >= 2000:
+        if (el > budget_s and n >= 2) or n >= max_steps:
             break
     return {"value": cfg.cells * n / el / 1e6, "unit": "Mcell-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"oracle (numpy FP64, 1 thread) on the 128x64x64 crop of the filter grid, "
-                      f"{n} steps in {el:.1f} s"}
+            "kind": "oracle", "steps": n, "seconds": round(el, 2),
+            "sample": f"oracle (numpy FP64, 1 thread) on {label}, {n} steps in {el:.1f} s"}
+
+
+# Paper-shaped configurations and their step counts for the oracle-vs-GPU table
+TABLE = [("slab64", lambda: W.slab64(), 200), ("filter_crop128", lambda: W.filter_crop(seed=0), 1000),
+         ("waveguide256", lambda: W.waveguide256(seed=0), 2000), ("design128", lambda: W.design128(seed=0), 400)]
+
+
+def run_table(budget_s, with_cpu):
+    """One JSON line per configuration: the GPU (FP64) over the whole step
+    count in one call, and with_cpu: the oracle over its first steps (as many
+    as fit in budget_s, from step 0) with the GPU timed over the same steps."""
+    import torch
+    import paper_2103_12819_amd as mm
+
+    def gpu_seconds(cfg, steps):
+        sim = mm.from_config(cfg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        el = time.perf_counter() - t0
+        iters = np.asarray(sim.stats())
+        sim.close()
+        return el, iters
+
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    print(json.dumps({"host": {"cpu_model": model, "logical_cpus": os.cpu_count(),
+                               "oracle_threads": 1, "device": torch.cuda.get_device_name(0)}}), flush=True)
+    gpu_seconds(W.slab64(), 3)     # first launches (code objects) outside the table
+    for name, make, steps in TABLE:
+        cfg = make()
+        el, iters = gpu_seconds(cfg, steps)
+        row = {"config": name, "n": list(cfg.n), "cells": cfg.cells, "steps": steps,
+               "gpu_fp64_s": round(el, 4), "gpu_fp64_Mcell_per_s": round(cfg.cells * steps / el / 1e6, 1),
+               "mean_iterations_per_substep": round(float(iters.mean()), 2)}
+        if with_cpu:
+            cb = cpu_baseline(budget_s, cfg=make(), label=f"{name}, from step 0", warm=False, max_steps=steps)
+            el_n, it_n = gpu_seconds(make(), cb["steps"])
+            row["oracle"] = cb
+            row["gpu_same_steps_Mcell_per_s"] = round(cfg.cells * cb["steps"] / el_n / 1e6, 1)
+            row["gpu_over_oracle_same_steps"] = round(row["gpu_same_steps_Mcell_per_s"] / cb["value"], 1)
+            row["mean_iterations_same_steps"] = round(float(it_n.mean()), 2)
+        print(json.dumps(row), flush=True)
 
 
 def main():
@@ -335,6 +387,9 @@ def main():
                     help="only run a plain 1 GiB device copy 5 times (scale reference for HBM counters)")
     ap.add_argument("--tiles-json", default=None,
                     help="write the workload's tile counts to this file and exit (GPU)")
+    ap.add_argument("--config-table", action="store_true",
+                    help="only time the paper-shaped configurations (GPU FP64, whole runs) and, without "
+                         "--no-cpu, the oracle on each one's first steps (one JSON line each)")
     ap.add_argument("--traffic-record", default=None, metavar="PMC_DIR",
                     help="write profiles/pmc_traffic.json from the counter runs under PMC_DIR (CPU)")
     args = ap.parse_args()
@@ -365,6 +420,9 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": src.numel() * 4, "bytes_written": dst.numel() * 4,
                           "launches": 6, "avg_ms": round(ms, 4),
                           "GB/s": round(2 * src.numel() * 4 / (ms / 1e3) / 1e9, 1)}), flush=True)
+        return
+    if args.config_table:
+        run_table(30.0, not args.no_cpu)
         return
     if args.tiles_json:
         import paper_2103_12819_amd as mm

@@ -106,15 +106,20 @@ def write_traffic_record(pmc_dir, workload="filter512"):
     lines = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read GB | write GB | "
              "algorithmic GB | traffic / algorithmic |", "|---|---|---|---|---|---|---|---|"]
     for short, pat in _PMC_NAMES:
-        fk = [k for k in fetch if pat in k]
-        wk = [k for k in write if pat in k]
-        if len(fk) != 1 or len(wk) != 1:
+        # one class may run as several instantiations (e_update over tile
+        # pairs and over unpaired tiles), each dispatched once per launch of
+        # the class: their per-dispatch means add up
+        fk = sorted(k for k in fetch if pat in k)
+        wk = sorted(k for k in write if pat in k)
+        if not fk or len(fk) != len(wk) or len({fetch[k][0] for k in fk}) != 1:
             continue
-        nf, f = fetch[fk[0]]
-        _, w = write[wk[0]]
+        nf = fetch[fk[0]][0]
+        f = sum(fetch[k][1] for k in fk)
+        w = sum(write[k][1] for k in wk)
         rd, wr = f * 1024 * scale["FETCH_SIZE"], w * 1024 * scale["WRITE_SIZE"]
-        ent = {"instantiation": fk[0].split("(")[0], "dispatches": nf, "read_bytes_per_launch": int(rd),
-               "write_bytes_per_launch": int(wr), "traffic_bytes_per_launch": int(rd + wr)}
+        ent = {"instantiation": " + ".join(k.split("(")[0] for k in fk), "dispatches": nf,
+               "read_bytes_per_launch": int(rd), "write_bytes_per_launch": int(wr),
+               "traffic_bytes_per_launch": int(rd + wr)}
         algo = "-"
         ratio = "-"
         if short in cells:

@@ -85,7 +85,10 @@ template <typename T> __device__ __forceinline__ double D(T v) { return (double)
 // each lands on.  Tile id = bx + gx (by + gy bz).  With split > 1 each tile
 // is cut along z into `split` runs of ceil(kc / split) planes, one block
 // each (blocks b = split * q + s: tile list[q], run s), for launches over
-// too few tiles to fill the chip.
+// too few tiles to fill the chip.  An e_update launch with blockDim.y = 8
+// takes two tiles stacked in y per block (the list holds the lower one): the
+// y halo of the upper tile is then the lower tile's last row, read by the
+// same block at the same plane, where separate blocks often miss it in L2.
 struct Tiles {
   const int* list;
   int gx, gy, kc, split;
@@ -122,8 +125,8 @@ __device__ __forceinline__ double src_term(const Src& s, int comp, int i, int j,
 // MAT: the cell maps come as a byte material id per cell and a table of
 // (eps_r, sigma) per id (exactly the values of the dense maps), staged in
 // LDS: 1 byte per cell instead of two map values.
-template <typename T, bool SIG, bool MAT>
-__global__ __launch_bounds__(256) void e_update(Geo g, T* __restrict__ Ex, T* __restrict__ Ey,
+template <typename T, bool SIG, bool MAT, int RY = 4>
+__global__ __launch_bounds__(64 * RY) void e_update(Geo g, T* __restrict__ Ex, T* __restrict__ Ey,
                                                T* __restrict__ Ez, const T* __restrict__ Hx,
                                                const T* __restrict__ Hy, const T* __restrict__ Hz,
                                                const T* __restrict__ eps_map, const T* __restrict__ sig_map,
@@ -143,10 +146,12 @@ __global__ __launch_bounds__(256) void e_update(Geo g, T* __restrict__ Ex, T* __
   __shared__ T teps[MAT ? 256 : 1], tsig[MAT ? 256 : 1], tca[MAT ? 256 : 1], tcb[MAT ? 256 : 1];
   if (MAT) {
     const int q = threadIdx.x + 64 * threadIdx.y;
-    const T e = mtab[q], sg = mtab[256 + q];
-    teps[q] = e;
-    tsig[q] = sg;
-    coef(e, e, e, e, sg, sg, sg, sg, tca[q], tcb[q]);
+    if (q < 256) {
+      const T e = mtab[q], sg = mtab[256 + q];
+      teps[q] = e;
+      tsig[q] = sg;
+      coef(e, e, e, e, sg, sg, sg, sg, tca[q], tcb[q]);
+    }
     __syncthreads();
   }
   int i, j, k0, k1;

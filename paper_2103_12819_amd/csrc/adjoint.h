@@ -499,4 +499,47 @@ __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T*
   }
 }
 
+
+// d L / d eps_r per cell: the transpose of the 4-cell edge mean, eps0 / 4
+// times each edge's cotangent (eb, FP64 on the padded layout), gathered over
+// the 12 edges that have the cell among their four -- per component, the
+// edges at the cell's two nodes along each transverse axis, skipping PEC
+// wall nodes and wrapping periodic ones -- in a fixed order.  Cells of the
+// planes k0 <= k < k0 + nk, x fastest, into out.
+__global__ __launch_bounds__(256) void adj_eps_cells(Geo g, const double* __restrict__ eb0,
+                                                     const double* __restrict__ eb1,
+                                                     const double* __restrict__ eb2, int k0, int nk,
+                                                     double* __restrict__ out) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long plane = (long long)g.nx * g.ny;
+  if (q >= plane * nk) return;
+  const int i = (int)(q % g.nx);
+  const long long r = q / g.nx;
+  const int j = (int)(r % g.ny), k = k0 + (int)(r / g.ny);
+  const int n[3] = {g.nx, g.ny, g.nz};
+  const bool per[3] = {(g.per & 1) != 0, (g.per & 2) != 0, (g.per & 4) != 0};
+  const double* eb[3] = {eb0, eb1, eb2};
+  double sum = 0.0;
+  for (int comp = 0; comp < 3; ++comp) {
+    const int t1 = comp == 0 ? 1 : 0, t2 = comp == 2 ? 1 : 2;
+    for (int u = 0; u < 2; ++u)
+      for (int v = 0; v < 2; ++v) {
+        int p[3] = {i, j, k};
+        p[t1] += u;
+        p[t2] += v;
+        bool interior = true;
+        for (int a = 0; a < 3; ++a) {
+          if (a == comp) continue;
+          if (per[a]) {
+            if (p[a] == n[a]) p[a] = 0;
+          } else if (p[a] == 0 || p[a] == n[a]) {
+            interior = false;
+          }
+        }
+        if (interior) sum += kEps0 * 0.25 * eb[comp][at(g, p[0], p[1], p[2])];
+      }
+  }
+  out[q] = sum;
+}
+
 }  // namespace mmk

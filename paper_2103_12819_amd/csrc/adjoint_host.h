@@ -472,39 +472,29 @@ mm_status adjoint_run(mm_ctx* c, int i0, double* grad_eps, double* grad_Ms) {
     }
   }
   HIPCHECK(c, hipStreamSynchronize(c->stream));
-  // ---- parameter chains (host) ----
+  // ---- parameter chains ----
   const size_t ncells = (size_t)c->nx * c->ny * c->nz;
-  std::fill(grad_eps, grad_eps + ncells, 0.0);
   std::fill(grad_Ms, grad_Ms + ncells, 0.0);
-  auto cidx = [&](int i, int j, int k) {
-    const int n[3] = {c->nx, c->ny, c->nz};
-    int p[3] = {i, j, k};
-    for (int a = 0; a < 3; ++a) {
-      if (p[a] < 0) p[a] += n[a];
-      if (p[a] >= n[a]) p[a] -= n[a];
-    }
-    return (size_t)p[0] + (size_t)c->nx * ((size_t)p[1] + (size_t)c->ny * p[2]);
-  };
   {
-    std::vector<double> eb(c->nelem);
-    for (int comp = 0; comp < 3; ++comp) {
-      HIPCHECK(c, hipMemcpy(eb.data(), w.epsb[comp], fd, hipMemcpyDeviceToHost));
-      const int t1 = comp == 0 ? 1 : 0, t2 = comp == 2 ? 1 : 2;
-      for (int k = 0; k < c->nz; ++k)
-        for (int j = 0; j < c->ny; ++j)
-          for (int i = 0; i < c->nx; ++i) {
-            if (!entry_interior(c, comp, i, j, k)) continue;
-            const double gv = mmk::kEps0 * 0.25 * eb[pidx(c, i, j, k)];
-            if (gv == 0.0) continue;
-            for (int u = 0; u < 2; ++u)
-              for (int v = 0; v < 2; ++v) {
-                int q[3] = {i, j, k};
-                q[t1] -= 1 - u;
-                q[t2] -= 1 - v;
-                grad_eps[cidx(q[0], q[1], q[2])] += gv;
-              }
-          }
+    // eps_r: gathered per cell on the device, a slab of planes at a time
+    // (at most ~8M cells, 64 MB), straight into the host array
+    const size_t plane = (size_t)c->nx * c->ny;
+    const int nk = (int)std::max<size_t>(1, std::min<size_t>((size_t)c->nz, ((size_t)1 << 23) / plane));
+    double* slab = (double*)dalloc(c, plane * nk * sizeof(double));
+    if (!slab) return fail(c, MM_ENOMEM, "adjoint: gradient slab allocation failed");
+    const Geo g = make_geo(c);
+    for (int k0 = 0; k0 < c->nz; k0 += nk) {
+      const int m = std::min(nk, c->nz - k0);
+      const size_t cnt = plane * m;
+      hipLaunchKernelGGL(mmk::adj_eps_cells, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, c->stream, g,
+                         (const double*)w.epsb[0], (const double*)w.epsb[1], (const double*)w.epsb[2], k0, m,
+                         slab);
+      HIPCHECK(c, hipGetLastError());
+      HIPCHECK(c, hipMemcpyAsync(grad_eps + plane * k0, slab, cnt * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+      HIPCHECK(c, hipStreamSynchronize(c->stream));
     }
+    dfree(c, slab);
   }
   if (!ntot) {
     s = copy_state(c, w.fin, false);
@@ -536,15 +526,17 @@ mm_status adjoint_run(mm_ctx* c, int i0, double* grad_eps, double* grad_Ms) {
     gtot += pr;
     double vb[3];
     for (int a = 0; a < 3; ++a) vb[a] = (Msf[t] / nv) * (m0b[a] - vh[a] * pr);
+    // cells with Ms = 0 keep a zero gradient (which faces are magnetic is
+    // held fixed), so an interface face adds to its magnetic cell only
     if (fc.b < 0) {   // one cell (PEC wall face)
-      grad_Ms[fc.a] += gtot + ((fc.ma[0] * vb[0] + fc.ma[1] * vb[1]) + fc.ma[2] * vb[2]);
+      if (c->cell_mag[fc.a]) grad_Ms[fc.a] += gtot + ((fc.ma[0] * vb[0] + fc.ma[1] * vb[1]) + fc.ma[2] * vb[2]);
     } else {
-      grad_Ms[fc.a] += 0.5 * gtot + 0.5 * ((fc.ma[0] * vb[0] + fc.ma[1] * vb[1]) + fc.ma[2] * vb[2]);
-      grad_Ms[fc.b] += 0.5 * gtot + 0.5 * ((fc.mb[0] * vb[0] + fc.mb[1] * vb[1]) + fc.mb[2] * vb[2]);
+      if (c->cell_mag[fc.a])
+        grad_Ms[fc.a] += 0.5 * gtot + 0.5 * ((fc.ma[0] * vb[0] + fc.ma[1] * vb[1]) + fc.ma[2] * vb[2]);
+      if (c->cell_mag[fc.b])
+        grad_Ms[fc.b] += 0.5 * gtot + 0.5 * ((fc.mb[0] * vb[0] + fc.mb[1] * vb[1]) + fc.mb[2] * vb[2]);
     }
   }
-  for (size_t q = 0; q < ncells; ++q)
-    if (!c->cell_mag[q]) grad_Ms[q] = 0.0;
   s = copy_state(c, w.fin, false);
   c->step = N;
   c->substep = sub0;

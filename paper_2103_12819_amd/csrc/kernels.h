@@ -86,9 +86,10 @@ template <typename T> __device__ __forceinline__ double D(T v) { return (double)
 // is cut along z into `split` runs of ceil(kc / split) planes, one block
 // each (blocks b = split * q + s: tile list[q], run s), for launches over
 // too few tiles to fill the chip.  An e_update launch with blockDim.y = 8
-// takes two tiles stacked in y per block (the list holds the lower one): the
-// y halo of the upper tile is then the lower tile's last row, read by the
-// same block at the same plane, where separate blocks often miss it in L2.
+// takes two tiles stacked in y per block (the list holds the lower one), so
+// one block streams both tiles' rows at each plane; the upper tile's y halo
+// is the lower tile's last row.  Measured 2 % faster than single tiles on
+// the 512 x 256 x 256 grid, for slightly more HBM reads.
 struct Tiles {
   const int* list;
   int gx, gy, kc, split;

@@ -23,9 +23,10 @@ def build(N, tol=1e-6, side=L, scheme=2):
     return from_config(W.convergence_cube(N, side=side, tol=tol), with_probes=False, scheme=scheme)
 
 
-def run(N, side=L, scheme=2):
+def run(N, side=L, scheme=2, steps=None):
+    """Fields after `steps` steps (default 5 N / 32, the paper's common time)."""
     sim = build(N, side=side, scheme=scheme)
-    sim.step(5 * N // 32)
+    sim.step(5 * N // 32 if steps is None else steps)
     out = {}
     for nm in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):
         out[nm] = sim.field(nm).transpose(2, 1, 0)

@@ -172,6 +172,25 @@ mm_status mm_init(mm_ctx **out, const mm_grid *g, double dt, const mm_materials 
  * then probe sampling at level n+1).  Asynchronous on the context's stream. */
 mm_status mm_step(mm_ctx *c, int64_t n);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mm_step
+ * without any allocation.  The sub-step control (final-count words, the
+ * completion barrier, the residual partials) lives in a fixed 4 MiB device
+ * array that the library holds on each device until the process ends,
+ * instead of in the context; the results are those of mm_step, bit for
+ * bit.  Everything else the steps write must already exist: the iteration
+ * log and the probe series storage are made (and grown) by mm_step, so a
+ * caller runs mm_step first for a step count at least as large.  Errors,
+ * before any work is enqueued: MM_ESTATE when probes were added after the
+ * last mm_step or adjoint checkpoints are enabled; MM_EINVAL when the steps
+ * would run past that storage or the control needs more than 4 MiB
+ * (2 x (max_iter + 2) x blocks x 8 bytes plus 256; max_iter 100 fits);
+ * MM_EDEVICE when the array's address could not be resolved at mm_init.
+ * Every call on one device shares that device's array: calls that overlap
+ * in time on one device (other streams, other threads) race and must not
+ * be issued.  Asynchronous on the context's stream, as mm_step. */
+mm_status mm_step_noalloc(mm_ctx *c, int64_t n);
+
 /* Probes.  kind 0: sample field `field` (see below) at staggered index
  * (i,j,k) after every step.  kind 1: Poynting flux through the node plane
  * x = i, P = dy dz sum_{j,k} [Ey Hz - Ez Hy] with Hz, Hy averaged from the

@@ -13,7 +13,7 @@ STATUS_NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EDEVICE",
 MM_BC_PEC, MM_BC_PERIODIC = 0, 1
 MM_FP64, MM_FP32 = 0, 1
 
-EXPORTED = ["mm_init", "mm_step", "mm_add_probe", "mm_add_hard_source", "mm_add_surface_current",
+EXPORTED = ["mm_init", "mm_step", "mm_step_noalloc", "mm_add_probe", "mm_add_hard_source", "mm_add_surface_current",
             "mm_probe", "mm_get_field", "mm_set_field", "mm_get_field_device", "mm_set_field_device",
             "mm_stats", "mm_sync", "mm_info", "mm_layout", "mm_adjoint_enable", "mm_adjoint", "mm_profile",
             "mm_profile_read", "mm_last_error", "mm_destroy"]
@@ -93,6 +93,8 @@ def load(path: str = LIB_PATH):
     lib.mm_init.restype = C.c_int
     lib.mm_step.argtypes = [P, C.c_int64]
     lib.mm_step.restype = C.c_int
+    lib.mm_step_noalloc.argtypes = [P, C.c_int64]
+    lib.mm_step_noalloc.restype = C.c_int
     lib.mm_add_probe.argtypes = [P, C.POINTER(mm_probe_desc), C.POINTER(C.c_int32)]
     lib.mm_add_probe.restype = C.c_int
     lib.mm_add_hard_source.argtypes = [P, C.POINTER(mm_hard_source)]

@@ -15,6 +15,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <unordered_set>
@@ -25,6 +26,10 @@
 #include "adjoint.h"
 
 using mmk::Geo;
+
+// Fixed device storage of mm_step_noalloc (see resolve_scratch).
+constexpr size_t kScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -106,6 +111,13 @@ struct mm_ctx {
   unsigned long long* d_part; // residual partials: 2 parities x nres iterations x step_blocks
   int nres;
   unsigned int* d_bar;        // barrier state of hm_finish
+  // the control words, partials and barrier state the sub-steps use: the
+  // three above, or the fixed device storage during mm_step_noalloc
+  unsigned long long* ctl_res;
+  unsigned long long* ctl_part;
+  unsigned int* ctl_bar;
+  void* scratch;              // this device's fixed storage (null if unresolved)
+  std::string scratch_err;
   int step_blocks, fin_blocks;
   int* h_ring;                // pinned: final iteration count of recent sub-steps
   int* d_ring;
@@ -206,6 +218,50 @@ mm_status fail(mm_ctx* c, mm_status s, const char* fmt, ...) {
     if (e_ != hipSuccess)                                                                \
       return fail(ctx, MM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));       \
   } while (0)
+
+// Fixed device storage for mm_step_noalloc, the entry point for callers
+// that cannot allocate: the sub-step control of such a call (two final-count
+// words, the barrier state of hm_finish, the residual partials) lives here
+// instead of in the context.  Each device holds its own copy until the
+// process ends; the host resolves its address once per device at mm_init
+// (the array's name in host code is not a device address).
+constexpr size_t kScratchHeader = 256;   // [0, 16) final counts, [64, 72) barrier
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices];
+
+// Bytes of sub-step control one call needs: header plus 2 parities x nres
+// iterations x step_blocks partials.
+size_t ctl_bytes(const mm_ctx* c) {
+  return kScratchHeader + 2 * (size_t)c->nres * (size_t)c->step_blocks * sizeof(unsigned long long);
+}
+
+// Once per device, with that device current: the address of `scratch`.
+void resolve_scratch(mm_ctx* c) {
+  c->scratch = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    c->scratch_err = e != hipSuccess ? hipGetErrorString(e) : "device ordinal out of range";
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      c->scratch_err = e != hipSuccess ? hipGetErrorString(e) : "null symbol address";
+      return;
+    }
+    g_scratch_addr[dev] = p;
+  }
+  c->scratch = g_scratch_addr[dev];
+}
+
+__global__ void zero_words(unsigned int* p, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = 0u;
+}
 
 void* dalloc(mm_ctx* c, size_t bytes) {
   if (bytes == 0) bytes = 8;
@@ -581,10 +637,10 @@ mm_status substep(mm_ctx* c, bool near_only = false, bool step3 = false) {
   const double h = 0.5 * c->dt;
   const double hmu0 = h / mmk::kMu0;
   mmk::Ctl C;
-  C.cur = c->d_res + (c->substep & 1);
-  C.next = c->d_res + ((c->substep + 1) & 1);
+  C.cur = c->ctl_res + (c->substep & 1);
+  C.next = c->ctl_res + ((c->substep + 1) & 1);
   C.P = c->step_blocks;
-  C.part = c->d_part + (size_t)(c->substep & 1) * c->nres * c->step_blocks;
+  C.part = c->ctl_part + (size_t)(c->substep & 1) * c->nres * c->step_blocks;
   C.tol = c->tol;
   C.max_iter = c->max_iter;
   C.fixed_iter = c->fixed_iter;
@@ -641,7 +697,7 @@ mm_status substep(mm_ctx* c, bool near_only = false, bool step3 = false) {
     {
       Timed tm(c, 4);
       hipLaunchKernelGGL((mmk::hm_finish<T>), dim3(c->fin_blocks), dim3(256), 0, c->stream, g, F, m, H0x, H0y,
-                         H0z, C, R + 1, c->d_bar, c->d_err);
+                         H0z, C, R + 1, c->ctl_bar, c->d_err);
     }
     {
       Timed tm(c, 6);
@@ -1364,6 +1420,9 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
   HIPCHECK(c, hipMemset(c->d_part, 0, 2 * (size_t)c->nres * c->step_blocks * sizeof(unsigned long long)));
   HIPCHECK(c, hipMemset(c->d_err, 0, sizeof(int)));
   HIPCHECK(c, hipMemset(c->d_bar, 0, 2 * sizeof(unsigned int)));
+  c->ctl_res = c->d_res;
+  c->ctl_part = c->d_part;
+  c->ctl_bar = c->d_bar;
   HIPCHECK(c, hipHostMalloc((void**)&c->h_ring, 64 * sizeof(int), hipHostMallocMapped));
   std::memset(c->h_ring, 0, 64 * sizeof(int));
   HIPCHECK(c, hipHostGetDevicePointer((void**)&c->d_ring, c->h_ring, 0));
@@ -1519,6 +1578,7 @@ mm_status mm_init(mm_ctx** out, const mm_grid* g, double dt, const mm_materials*
   c->ualloc = opt->dev_alloc;
   c->ufree = opt->dev_free;
   c->actx = opt->alloc_ctx;
+  resolve_scratch(c);
   mm_status s = setup_pml(c, opt->pml);
   if (s == MM_OK) s = build(c, mat, src);
   if (s == MM_OK) {
@@ -1544,6 +1604,50 @@ mm_status mm_step(mm_ctx* c, int64_t n) {
   s = grow_buffers(c, (size_t)(c->step + n));
   if (s) return s;
   return c->prec == MM_FP32 ? run_steps<float>(c, n) : run_steps<double>(c, n);
+}
+
+mm_status mm_step_noalloc(mm_ctx* c, int64_t n) {
+  if (!c) return MM_EINVAL;
+  if (n < 0) return fail(c, MM_EINVAL, "negative step count");
+  if (n == 0) return MM_OK;
+  if (!c->scratch)
+    return fail(c, MM_EDEVICE, "mm_step_noalloc: the fixed device storage was not resolved at init (%s)",
+                c->scratch_err.c_str());
+  if (!c->probes.empty() && !c->probes_frozen)
+    return fail(c, MM_ESTATE, "mm_step_noalloc: probes added since the last mm_step have no storage yet "
+                              "(mm_step creates it)");
+  if (c->ckpt_every > 0)
+    return fail(c, MM_ESTATE, "mm_step_noalloc: adjoint checkpoints are enabled; they need mm_step");
+  const size_t need = (size_t)c->step + (size_t)n;
+  const size_t cap_steps = std::min(c->iters_cap / 2, c->probes.empty() ? SIZE_MAX : c->series_cap);
+  if (need > cap_steps)
+    return fail(c, MM_EINVAL,
+                "mm_step_noalloc: %lld steps would end at step %zu, beyond the iteration-log and probe "
+                "storage made by earlier mm_step calls (%zu steps)",
+                (long long)n, need, cap_steps);
+  const size_t bytes = ctl_bytes(c);
+  if (bytes > kScratchBytes)
+    return fail(c, MM_EINVAL,
+                "mm_step_noalloc: the sub-step control needs %zu bytes (max_iter %d, %d blocks), above the "
+                "fixed %zu bytes",
+                bytes, c->max_iter, c->step_blocks, kScratchBytes);
+  unsigned char* base = (unsigned char*)c->scratch;
+  // the final-count words and the barrier state start at zero; the
+  // partials are written before they are read
+  hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, c->stream, (unsigned int*)base,
+                     (int)(kScratchHeader / sizeof(unsigned int)));
+  HIPCHECK(c, hipGetLastError());
+  unsigned long long* res = c->ctl_res;
+  unsigned long long* part = c->ctl_part;
+  unsigned int* bar = c->ctl_bar;
+  c->ctl_res = (unsigned long long*)base;
+  c->ctl_bar = (unsigned int*)(base + 64);
+  c->ctl_part = (unsigned long long*)(base + kScratchHeader);
+  const mm_status s = c->prec == MM_FP32 ? run_steps<float>(c, n) : run_steps<double>(c, n);
+  c->ctl_res = res;
+  c->ctl_part = part;
+  c->ctl_bar = bar;
+  return s;
 }
 
 namespace {

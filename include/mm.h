@@ -155,6 +155,13 @@ typedef struct {
                              (one explicit Landau-Lifshitz step of M per half step,
                              then eq:H_update; tol, max_iter and fixed_iter unused) */
   const mm_pml *pml;      /* NULL: no open boundary */
+  int32_t fused;          /* H-M sub-step form: 0 automatic (fused for at least 2^18
+                             evolving magnetic faces), 1 fused whenever allowed, -1
+                             never.  Fused: iterations 1-3 of a sub-step in one
+                             launch, pipelined along z with the iterates on chip
+                             (same results, bit for bit); allowed with the
+                             second-order scheme, no open boundary, no hard H
+                             source or surface current, under 2^24 magnetic faces */
 } mm_options;
 
 typedef struct mm_ctx mm_ctx;
@@ -304,8 +311,9 @@ mm_status mm_adjoint(mm_ctx *c, int32_t probe_id, double *grad_eps_r, double *gr
 /* Kernel timing.  mm_profile(c, 1) makes every later mm_step bracket each
  * kernel launch with a pair of HIP events on the context's stream (class
  * 0 e_update, 1 h_bulk (one half step: every tile, or the near tiles),
- * 2 hm_pre, 3 hm_step, 4 hm_finish, 5 probes, 6 hm_commit, 7 h_far (the
- * fused two half steps of the far tiles)); mm_profile(c, 0) stops
+ * 2 hm_pre or hm_fused, 3 hm_step or hm_more, 4 hm_finish, 5 probes,
+ * 6 hm_commit, 7 h_far (the fused two half steps of the far tiles)),
+ * mm_profile(c, 0) stops
  * recording.  mm_profile_read synchronises, writes the summed elapsed
  * milliseconds and the launch counts of each class to ms[0..7] /
  * counts[0..7] and discards the records. */

@@ -85,14 +85,15 @@ class Sim:
     precision 'fp64' or 'fp32', tol, max_iter, fixed_iter, `scheme` 2
     (second-order, iterative) or 1 (first-order), and `pml`: None or
     (cells, R0, order), cells = layer thicknesses (x_lo, x_hi, y_lo, y_hi,
-    z_lo, z_hi) (see mm_pml).  `stream` is a raw hipStream_t (int) or None
-    for torch's current stream.
+    z_lo, z_hi) (see mm_pml), `fused` 0 / 1 / -1 (automatic, on, off: see
+    mm_options.fused).  `stream` is a raw hipStream_t (int) or None for
+    torch's current stream.
     """
 
     def __init__(self, n, d, dt, eps_r=None, sigma=None, mu_r=None, Ms=None, alpha=None,
                  gamma=None, m0_dir=None, H0=(0.0, 0.0, 0.0), source=None,
                  periodic=(False, False, False), precision="fp64", tol=1e-10, max_iter=100,
-                 fixed_iter=0, stream=None, torch_alloc=True, scheme=2, pml=None):
+                 fixed_iter=0, stream=None, torch_alloc=True, scheme=2, pml=None, fused=0):
         self._lib = N.load()
         self._ctx = C.c_void_p()
         g = N.mm_grid(int(n[0]), int(n[1]), int(n[2]),
@@ -120,6 +121,7 @@ class Sim:
         opt.max_iter = int(max_iter)
         opt.fixed_iter = int(fixed_iter)
         opt.scheme = int(scheme)
+        opt.fused = int(fused)
         if pml is not None:
             cells, R0, order = pml
             self._pml = N.mm_pml((C.c_int32 * 6)(*[int(v) for v in cells]), float(R0), float(order))

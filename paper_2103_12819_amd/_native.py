@@ -63,7 +63,7 @@ class mm_options(C.Structure):
     _fields_ = [("prec", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("fixed_iter", C.c_int32), ("hip_stream", C.c_void_p),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p),
-                ("scheme", C.c_int32), ("pml", C.POINTER(mm_pml))]
+                ("scheme", C.c_int32), ("pml", C.POINTER(mm_pml)), ("fused", C.c_int32)]
 
 
 class mm_probe_desc(C.Structure):

@@ -1086,6 +1086,7 @@ __global__ __launch_bounds__(MM_MAG_THREADS) void hm_commit(Fields<T> F, Mag m, 
 template <typename T>
 struct Lag {
   const unsigned char* far;
+  const T* Hn[3];  // or null: where the other (near) tiles' H is, during a fused run
   const T* mu;    // cell mu_r, or null when mu_r = 1 everywhere
   T coef0, h;     // dt / (2 mu0) and dt / 2
   int gx, gy, kc;
@@ -1099,8 +1100,9 @@ template <typename T>
 __device__ double h_level(const Geo& g, const Fields<T>& F, const Lag<T>& L, int f, int i, int j, int k) {
   const int c = at(g, i, j, k);
   const T hv = tri(F.H)(f)[c];
-  if (!L.far || i >= g.nx || j >= g.ny || k >= g.nz) return D(hv);
-  if (!L.far[(i >> 6) + L.gx * ((j >> 2) + L.gy * (k / L.kc))]) return D(hv);
+  if (i >= g.nx || j >= g.ny || k >= g.nz) return D(hv);   // PEC wall faces: zero in both buffers
+  if (!L.far || !L.far[(i >> 6) + L.gx * ((j >> 2) + L.gy * (k / L.kc))])
+    return L.Hn[0] ? D(L.Hn[f][c]) : D(hv);
   const bool pxp = g.per & 1, pyp = g.per & 2, pzp = g.per & 4;
   const T idx = (T)g.idx, idy = (T)g.idy, idz = (T)g.idz;
   const T sdx = (T)g.dx, sdy = (T)g.dy, sdz = (T)g.dz;

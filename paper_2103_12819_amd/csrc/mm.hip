@@ -23,6 +23,7 @@
 
 #include "../../include/mm.h"
 #include "kernels.h"
+#include "hm_fused.h"
 #include "adjoint.h"
 
 using mmk::Geo;
@@ -118,6 +119,22 @@ struct mm_ctx {
   unsigned int* ctl_bar;
   void* scratch;              // this device's fixed storage (null if unresolved)
   std::string scratch_err;
+  int* ctl_kpred;             // fused form: previous sub-step's iteration count
+  unsigned long long* ctl_fpart;  // fused form: partials of hm_fused (2 parities x 4 rows x chunks)
+
+  // fused H-M sub-step (hm_fused.h): chunks of 60 x 4 columns x fL planes
+  // holding evolving faces, their slot tables, the second M buffer (Step 1
+  // writes it, Step 3 writes d_M back) and the device-side count
+  int fuse_mode;              // mm_options.fused
+  bool fused_ok;              // the configuration allows the fused form (chunks built)
+  bool chain_fused;           // the current run of steps uses it
+  int nchunks, fL;
+  int* d_forg;
+  unsigned* d_fslots;
+  double* d_Mb[3];
+  unsigned long long* d_fpart;
+  int* d_kpred;
+  std::vector<unsigned char> h_nbm;
   int step_blocks, fin_blocks;
   int* h_ring;                // pinned: final iteration count of recent sub-steps
   int* d_ring;
@@ -225,7 +242,7 @@ mm_status fail(mm_ctx* c, mm_status s, const char* fmt, ...) {
 // instead of in the context.  Each device holds its own copy until the
 // process ends; the host resolves its address once per device at mm_init
 // (the array's name in host code is not a device address).
-constexpr size_t kScratchHeader = 256;   // [0, 16) final counts, [64, 72) barrier
+constexpr size_t kScratchHeader = 256;   // [0, 16) final counts, [64, 72) barrier, [128, 132) count
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void* g_scratch_addr[kMaxDevices];
@@ -233,7 +250,8 @@ void* g_scratch_addr[kMaxDevices];
 // Bytes of sub-step control one call needs: header plus 2 parities x nres
 // iterations x step_blocks partials.
 size_t ctl_bytes(const mm_ctx* c) {
-  return kScratchHeader + 2 * (size_t)c->nres * (size_t)c->step_blocks * sizeof(unsigned long long);
+  return kScratchHeader + 2 * (size_t)c->nres * (size_t)c->step_blocks * sizeof(unsigned long long) +
+         2 * 4 * (size_t)c->nchunks * sizeof(unsigned long long);
 }
 
 // Once per device, with that device current: the address of `scratch`.
@@ -261,6 +279,10 @@ void resolve_scratch(mm_ctx* c) {
 __global__ void zero_words(unsigned int* p, int n) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) p[t] = 0u;
+}
+
+__global__ void copy_word(int* dst, const int* src) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
 }
 
 void* dalloc(mm_ctx* c, size_t bytes) {
@@ -627,11 +649,123 @@ mm_status apply_hard(mm_ctx* c, bool e_field, double t) {
   return MM_OK;
 }
 
+// The fused form of one H-M sub-step (hm_fused.h).  Within a run of steps
+// the near tiles' H alternates between H (Step 1 writes it, so the E update
+// reads it) and the shadow A (Step 3 writes it), M between d_M (Step 3) and
+// d_Mb (Step 1); the far tiles stay in H.  run_steps copies the near tiles
+// H -> A when a run starts and A -> H when it ends.
+template <typename T>
+mm_status substep_fused(mm_ctx* c, bool near_only, bool step3) {
+  const Geo g = make_geo(c);
+  const double h = 0.5 * c->dt;
+  const double hmu0 = h / mmk::kMu0;
+  T* X[3];
+  T* Y[3];
+  for (int a = 0; a < 3; ++a) {
+    X[a] = (T*)c->H[a];
+    Y[a] = (T*)c->A[a];
+  }
+  T** Hin = step3 ? X : Y;
+  T** Hout = step3 ? Y : X;
+  double** Min = step3 ? c->d_Mb : c->d_M;
+  double** Mout = step3 ? c->d_M : c->d_Mb;
+  if (c->n_near > 0) {
+    const int split = split_for(c, c->n_near);
+    const mmk::Tiles tl = tiles(c, c->d_tl_near, split);
+    Timed tm(c, 1);
+#define MM_HDB(MU)                                                                                           \
+  hipLaunchKernelGGL((mmk::h_half_db<T, MU>), dim3(c->n_near * split), dim3(64, 4), 0, c->stream, g, Hin[0], \
+                     Hin[1], Hin[2], Hout[0], Hout[1], Hout[2], (const T*)c->E[0], (const T*)c->E[1],        \
+                     (const T*)c->E[2], (const T*)c->mu, (T)hmu0, (T)h, tl)
+    if (c->mu) MM_HDB(true);
+    else MM_HDB(false);
+#undef MM_HDB
+  }
+  if (!near_only && c->n_far > 0) {
+    const int split = split_for(c, c->n_far);
+    const mmk::Tiles tl = tiles(c, c->d_tl_far, split);
+    Timed tm(c, 1);
+#define MM_HFAR1(MU)                                                                                          \
+  hipLaunchKernelGGL((mmk::h_bulk<T, MU, 1>), dim3(c->n_far * split), dim3(64, 4), 0, c->stream, g, X[0],      \
+                     X[1], X[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2], (const T*)c->mu,    \
+                     (T)hmu0, (T)h, tl)
+    if (c->mu) MM_HFAR1(true);
+    else MM_HFAR1(false);
+#undef MM_HFAR1
+  }
+  HIPCHECK(c, hipGetLastError());
+  mmk::Mag m = make_mag(c);
+  m.hlog = nullptr;
+  m.hlog_cap = 0;
+  unsigned long long* fpart = c->ctl_fpart + (size_t)(c->substep & 1) * 4 * c->nchunks;
+  {
+    mmk::FusedArgs<T> a;
+    for (int q = 0; q < 3; ++q) {
+      a.Hin[q] = Hin[q];
+      a.Hout[q] = Hout[q];
+      a.E[q] = (const T*)c->E[q];
+      a.Min[q] = Min[q];
+      a.Mout[q] = Mout[q];
+    }
+    a.slots = c->d_fslots;
+    a.org = c->d_forg;
+    a.L = c->fL;
+    a.nfmat = c->nfmat;
+    a.kfix = c->fixed_iter;
+    a.kpred = c->ctl_kpred;
+    a.m = m;
+    a.H0x = c->H0[0];
+    a.H0y = c->H0[1];
+    a.H0z = c->H0[2];
+    a.hmu0 = hmu0;
+    a.part = fpart;
+    a.P = c->nchunks;
+    Timed tm(c, 2);
+    hipLaunchKernelGGL((mmk::hm_fused<T>), dim3(c->nchunks), dim3(mmk::kFCols), 0, c->stream, g, a);
+  }
+  HIPCHECK(c, hipGetLastError());
+  {
+    mmk::MoreArgs<T> b;
+    for (int q = 0; q < 3; ++q) {
+      b.Hin[q] = Hin[q];
+      b.Hout[q] = Hout[q];
+      b.S[q] = (T*)c->B[q];
+      b.E[q] = (const T*)c->E[q];
+      b.Min[q] = Min[q];
+      m.M[q] = Mout[q];
+    }
+    b.m = m;
+    b.H0x = c->H0[0];
+    b.H0y = c->H0[1];
+    b.H0z = c->H0[2];
+    b.hmu0 = hmu0;
+    b.fpart = fpart;
+    b.Pf = c->nchunks;
+    b.kfix = c->fixed_iter;
+    b.kpred = c->ctl_kpred;
+    mmk::Ctl C;
+    C.cur = c->ctl_res + (c->substep & 1);
+    C.next = c->ctl_res + ((c->substep + 1) & 1);
+    C.P = c->step_blocks;
+    C.part = c->ctl_part + (size_t)(c->substep & 1) * c->nres * c->step_blocks;
+    C.tol = c->tol;
+    C.max_iter = c->max_iter;
+    C.fixed_iter = c->fixed_iter;
+    Timed tm(c, 3);
+    hipLaunchKernelGGL((mmk::hm_more<T>), dim3(c->fin_blocks), dim3(256), 0, c->stream, g, b, C,
+                       c->d_iters + c->substep, c->d_ring + (c->substep & 63), c->ctl_bar, c->d_err);
+  }
+  HIPCHECK(c, hipGetLastError());
+  c->substep++;
+  return MM_OK;
+}
+
 // One H-M sub-step (Step 1, or Step 3 when step3).  near_only: the Faraday
 // half step runs on the near tiles only (the far tiles take it inside the
 // fused pass of h_far).
 template <typename T>
 mm_status substep(mm_ctx* c, bool near_only = false, bool step3 = false) {
+  if (c->chain_fused) return substep_fused<T>(c, near_only, step3);
   Geo g = make_geo(c);
   mmk::Fields<T> F = make_fields<T>(c);
   const double h = 0.5 * c->dt;
@@ -799,6 +933,7 @@ mm_status record_probes(mm_ctx* c, bool lagged = false) {
   const mmk::Fields<T> F = make_fields<T>(c);
   mmk::Lag<T> L;
   L.far = (lagged && c->n_far > 0) ? c->d_far : nullptr;
+  for (int a = 0; a < 3; ++a) L.Hn[a] = (lagged && c->chain_fused) ? (const T*)c->A[a] : nullptr;
   L.mu = (const T*)c->mu;
   L.h = (T)(0.5 * c->dt);
   L.coef0 = (T)(0.5 * c->dt / mmk::kMu0);
@@ -840,6 +975,31 @@ mm_status save_checkpoint(mm_ctx* c, size_t idx);
 // step of the call) and ends one when it must leave them there (last step,
 // or a checkpoint before the next step); inside a chain the far tiles skip
 // Step 1 and Step 3 and take the fused pass after the probes instead.
+// Copy the near tiles' H between the field arrays and the shadow A (the
+// fused form's second buffer).
+template <typename T>
+mm_status copy_near(mm_ctx* c, bool to_shadow) {
+  if (c->n_near == 0) return MM_OK;
+  const Geo g = make_geo(c);
+  const int split = split_for(c, c->n_near);
+  const mmk::Tiles tl = tiles(c, c->d_tl_near, split);
+  void* const* src = to_shadow ? c->H : c->A;
+  void* const* dst = to_shadow ? c->A : c->H;
+  hipLaunchKernelGGL((mmk::copy_tiles<T>), dim3(c->n_near * split), dim3(64, 4), 0, c->stream, g,
+                     (const T*)src[0], (const T*)src[1], (const T*)src[2], (T*)dst[0], (T*)dst[1], (T*)dst[2], tl);
+  HIPCHECK(c, hipGetLastError());
+  return MM_OK;
+}
+
+// Whether the next run of steps takes the fused sub-step.
+bool fused_for_chain(const mm_ctx* c) {
+  if (!c->fused_ok || c->adj_recompute || c->hlog_cur) return false;
+  if (c->fixed_iter > mmk::kFMaxK) return false;
+  for (const HardSrc& hs : c->hard)
+    if (hs.field >= 3) return false;
+  return true;
+}
+
 template <typename T>
 mm_status run_steps(mm_ctx* c, int64_t n) {
   mm_status s;
@@ -850,9 +1010,17 @@ mm_status run_steps(mm_ctx* c, int64_t n) {
       if (s) return s;
     }
     const bool end = q == n - 1 || (c->ckpt_every > 0 && (c->step + 1) % c->ckpt_every == 0);
+    if (!lagging) {   // a run starts: every tile at level n, everything in H
+      c->chain_fused = fused_for_chain(c);
+      if (c->chain_fused && (s = copy_near<T>(c, true))) return s;
+    }
     if ((s = substep<T>(c, lagging))) return s;     // Step 1
     if ((s = e_step<T>(c))) return s;               // Step 2
     if ((s = substep<T>(c, !end, true))) return s;  // Step 3
+    if (end && c->chain_fused) {
+      if ((s = copy_near<T>(c, false))) return s;
+      c->chain_fused = false;
+    }
     if ((s = record_probes<T>(c, !end))) return s;
     if (!end && (s = h_far<T>(c))) return s;
     lagging = !end;
@@ -1140,6 +1308,135 @@ mm_status build_tiles(mm_ctx* c) {
   return MM_OK;
 }
 
+// Chunks of the fused H-M sub-step: 30 x 6 columns x fL planes holding at
+// least one evolving face, in XCD order, and for each chunk its slot table
+// over the 32 x 8 x (fL + 2) cells of chunk and one-cell rim (per family:
+// the face's list index and neighbour mask, or kNoFace).  fL is picked from
+// 4..32 for the fewest chunk rounds over the CUs times pipeline steps.
+mm_status build_fused(mm_ctx* c) {
+  c->fused_ok = false;
+  c->chain_fused = false;
+  c->nchunks = 0;
+  c->fL = 0;
+  if (c->fuse_mode < 0 || c->scheme != 2 || c->nmag == 0 || c->has_pml) return MM_OK;
+  if ((size_t)c->nmag + c->nwall >= (size_t(1) << 24)) return MM_OK;
+  if (c->fuse_mode == 0 && c->nmag < (1 << 18)) return MM_OK;
+  int dev = 0, ncu = 1;
+  HIPCHECK(c, hipGetDevice(&dev));
+  HIPCHECK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  using mmk::kFCols;
+  using mmk::kFIX;
+  using mmk::kFIY;
+  using mmk::kFX;
+  const int n3[3] = {c->nx, c->ny, c->nz};
+  auto cell_of = [&](int t, int& i, int& j, int& k) {
+    const int pi = c->h_idx[t];
+    k = pi / (c->px * c->py);
+    const int rr = pi - k * c->px * c->py;
+    j = rr / c->px;
+    i = rr - j * c->px;
+  };
+  auto chunks_for = [&](int L) {
+    std::vector<long long> keys;
+    keys.reserve(c->nmag / 16 + 16);
+    const long long gx = (c->nx + kFIX - 1) / kFIX, gy = (c->ny + kFIY - 1) / kFIY;
+    for (int t = 0; t < c->nmag; ++t) {
+      int i, j, k;
+      cell_of(t, i, j, k);
+      keys.push_back((long long)(i / kFIX) + gx * ((long long)(j / kFIY) + gy * (long long)(k / L)));
+    }
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    return keys;
+  };
+  int bestL = 4;
+  long long bestCost = -1;
+  for (int L : {4, 8, 16, 32}) {
+    const long long n = (long long)chunks_for(L).size();
+    const long long cost = ((n + 2 * ncu - 1) / (2 * ncu)) * (L + 3);   // two chunks per CU
+    if (bestCost < 0 || cost < bestCost) {
+      bestCost = cost;
+      bestL = L;
+    }
+  }
+  const int L = bestL;
+  const std::vector<long long> keys = chunks_for(L);
+  std::vector<int> nat(keys.size());
+  for (size_t q = 0; q < keys.size(); ++q) nat[q] = (int)q;
+  const std::vector<int> ord = xcd_order(nat);
+  const long long gx = (c->nx + kFIX - 1) / kFIX, gy = (c->ny + kFIY - 1) / kFIY;
+  const int NC = (int)keys.size();
+  std::vector<int> org(3 * (size_t)NC);
+  for (int b = 0; b < NC; ++b) {
+    const long long key = keys[ord[b]];
+    org[3 * b] = (int)(key % gx) * kFIX;
+    org[3 * b + 1] = (int)((key / gx) % gy) * kFIY;
+    org[3 * b + 2] = (int)(key / (gx * gy)) * L;
+  }
+  // face lookup: (family, padded index) -> list index of the evolving face
+  const bool dense = c->nelem <= (size_t(64) << 20);
+  std::vector<int> dmap;
+  std::unordered_map<long long, int> hmap;
+  if (dense) {
+    dmap.assign(3 * c->nelem, -1);
+    for (int t = 0; t < c->nmag; ++t) dmap[(size_t)c->h_fam[t] * c->nelem + c->h_idx[t]] = t;
+  } else {
+    hmap.reserve((size_t)c->nmag * 2);
+    for (int t = 0; t < c->nmag; ++t) hmap[(long long)c->h_fam[t] * (long long)c->nelem + c->h_idx[t]] = t;
+  }
+  auto lookup = [&](int f, size_t pi) -> int {
+    if (dense) return dmap[(size_t)f * c->nelem + pi];
+    auto it = hmap.find((long long)f * (long long)c->nelem + (long long)pi);
+    return it == hmap.end() ? -1 : it->second;
+  };
+  const int EP = L + 2;
+  const size_t per_chunk = (size_t)EP * 3 * kFCols;
+  std::vector<unsigned> slots(per_chunk * NC, mmk::kNoFace);
+  for (int b = 0; b < NC; ++b) {
+    unsigned* sl = slots.data() + per_chunk * b;
+    for (int e = 0; e < EP; ++e)
+      for (int col = 0; col < kFCols; ++col) {
+        const int u[3] = {org[3 * b] - 1 + col % kFX, org[3 * b + 1] - 1 + col / kFX, org[3 * b + 2] - 1 + e};
+        int w[3];
+        bool ok = true;
+        for (int a = 0; a < 3 && ok; ++a) {
+          if (c->per >> a & 1) w[a] = ((u[a] % n3[a]) + n3[a]) % n3[a];
+          else if (u[a] < 0 || u[a] >= n3[a]) ok = false;
+          else w[a] = u[a];
+        }
+        if (!ok) continue;
+        const size_t pi = pidx(c, w[0], w[1], w[2]);
+        for (int f = 0; f < 3; ++f) {
+          const int t = lookup(f, pi);
+          if (t >= 0) sl[((size_t)e * 3 + f) * kFCols + col] = ((unsigned)t << 8) | c->h_nbm[t];
+        }
+      }
+  }
+  c->d_forg = (int*)dalloc(c, org.size() * sizeof(int));
+  c->d_fslots = (unsigned*)dalloc(c, slots.size() * sizeof(unsigned));
+  c->d_fpart = (unsigned long long*)dalloc(c, 2 * 4 * (size_t)NC * sizeof(unsigned long long));
+  c->d_kpred = (int*)dalloc(c, sizeof(int));
+  const size_t ntot = (size_t)c->nmag + c->nwall;
+  for (int a = 0; a < 3; ++a) {
+    c->d_Mb[a] = (double*)dalloc(c, ntot * sizeof(double));
+    if (!c->d_Mb[a]) return fail(c, MM_ENOMEM, "allocation of the second M buffer failed");
+    HIPCHECK(c, hipMemcpy(c->d_Mb[a], c->d_M[a], ntot * sizeof(double), hipMemcpyDeviceToDevice));
+  }
+  if (!c->d_forg || !c->d_fslots || !c->d_fpart || !c->d_kpred)
+    return fail(c, MM_ENOMEM, "allocation of the fused sub-step tables failed");
+  HIPCHECK(c, hipMemcpy(c->d_forg, org.data(), org.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHECK(c, hipMemcpy(c->d_fslots, slots.data(), slots.size() * sizeof(unsigned), hipMemcpyHostToDevice));
+  HIPCHECK(c, hipMemset(c->d_fpart, 0, 2 * 4 * (size_t)NC * sizeof(unsigned long long)));
+  const int one = 1;
+  HIPCHECK(c, hipMemcpy(c->d_kpred, &one, sizeof(int), hipMemcpyHostToDevice));
+  c->ctl_kpred = c->d_kpred;
+  c->ctl_fpart = c->d_fpart;
+  c->nchunks = NC;
+  c->fL = L;
+  c->fused_ok = true;
+  return MM_OK;
+}
+
 mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
   const size_t ncells = (size_t)c->nx * c->ny * c->nz;
   const bool fp32 = c->prec == MM_FP32;
@@ -1358,6 +1655,7 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
         nbm[t] = mk;
       }
       HIPCHECK(c, hipMemcpy(c->d_nbm, nbm.data(), ntot, hipMemcpyHostToDevice));
+      c->h_nbm = nbm;
     }
     HIPCHECK(c, hipMemcpy(c->d_idx, c->h_idx.data(), ntot * sizeof(int), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(c->d_Ms, hv[0].data(), ntot * sizeof(double), hipMemcpyHostToDevice));
@@ -1423,6 +1721,10 @@ mm_status build(mm_ctx* c, const mm_materials* mat, const mm_source* src) {
   c->ctl_res = c->d_res;
   c->ctl_part = c->d_part;
   c->ctl_bar = c->d_bar;
+  {
+    mm_status fs = build_fused(c);
+    if (fs) return fs;
+  }
   HIPCHECK(c, hipHostMalloc((void**)&c->h_ring, 64 * sizeof(int), hipHostMallocMapped));
   std::memset(c->h_ring, 0, 64 * sizeof(int));
   HIPCHECK(c, hipHostGetDevicePointer((void**)&c->d_ring, c->h_ring, 0));
@@ -1525,6 +1827,7 @@ mm_status mm_init(mm_ctx** out, const mm_grid* g, double dt, const mm_materials*
     return bad("iteration options");
   if (opt->prec != MM_FP64 && opt->prec != MM_FP32) return bad("precision");
   if (opt->scheme != 0 && opt->scheme != 1 && opt->scheme != 2) return bad("scheme");
+  if (opt->fused < -1 || opt->fused > 1) return bad("fused");
   if (opt->pml) {
     const int n3[3] = {g->nx, g->ny, g->nz};
     bool any = false;
@@ -1572,6 +1875,7 @@ mm_status mm_init(mm_ctx** out, const mm_grid* g, double dt, const mm_materials*
   c->max_iter = opt->max_iter;
   c->fixed_iter = opt->fixed_iter;
   c->scheme = opt->scheme == 1 ? 1 : 2;
+  c->fuse_mode = opt->fused;
   if (c->scheme == 1) c->fixed_iter = 1;   // one explicit update per sub-step
   for (int a = 0; a < 3; ++a) c->H0[a] = bias ? bias->H0[a] : 0.0;
   c->stream = (hipStream_t)opt->hip_stream;
@@ -1640,13 +1944,24 @@ mm_status mm_step_noalloc(mm_ctx* c, int64_t n) {
   unsigned long long* res = c->ctl_res;
   unsigned long long* part = c->ctl_part;
   unsigned int* bar = c->ctl_bar;
+  int* kpred = c->ctl_kpred;
+  unsigned long long* fpart = c->ctl_fpart;
   c->ctl_res = (unsigned long long*)base;
   c->ctl_bar = (unsigned int*)(base + 64);
   c->ctl_part = (unsigned long long*)(base + kScratchHeader);
+  if (c->fused_ok) {
+    // the fused form's count prediction carries over from the context
+    c->ctl_kpred = (int*)(base + 128);
+    c->ctl_fpart = c->ctl_part + 2 * (size_t)c->nres * c->step_blocks;
+    hipLaunchKernelGGL(copy_word, dim3(1), dim3(64), 0, c->stream, c->ctl_kpred, kpred);
+  }
   const mm_status s = c->prec == MM_FP32 ? run_steps<float>(c, n) : run_steps<double>(c, n);
+  if (c->fused_ok) hipLaunchKernelGGL(copy_word, dim3(1), dim3(64), 0, c->stream, kpred, c->ctl_kpred);
   c->ctl_res = res;
   c->ctl_part = part;
   c->ctl_bar = bar;
+  c->ctl_kpred = kpred;
+  c->ctl_fpart = fpart;
   return s;
 }
 

@@ -77,7 +77,7 @@ def test_struct_layouts_match_the_header():
     assert C.sizeof(N.mm_materials) == 7 * 8
     assert C.sizeof(N.mm_bias) == 24
     assert C.sizeof(N.mm_source) == 40
-    assert C.sizeof(N.mm_options) == 72
+    assert C.sizeof(N.mm_options) == 80
     assert C.sizeof(N.mm_pml) == 40
     assert C.sizeof(N.mm_hard_source) == 40
     assert C.sizeof(N.mm_surface_current) == 48
@@ -85,7 +85,7 @@ def test_struct_layouts_match_the_header():
 
 
 def _init(lib, n=(8, 4, 4), d=(1e-6,) * 3, dt=None, tol=1e-10, max_iter=10, prec=0, Ms=None,
-          eps=None, bc=(0, 0, 0), scheme=0, pml=None):
+          eps=None, bc=(0, 0, 0), scheme=0, pml=None, fused=0):
     ctx = C.c_void_p()
     g = N.mm_grid(n[0], n[1], n[2], (C.c_int32 * 3)(*bc), d[0], d[1], d[2])
     keep = [] if Ms is None else [Ms]
@@ -96,7 +96,7 @@ def _init(lib, n=(8, 4, 4), d=(1e-6,) * 3, dt=None, tol=1e-10, max_iter=10, prec
         keep.append(eps)
         mat.eps_r = eps.ctypes.data_as(C.POINTER(C.c_double))
     opt = N.mm_options()
-    opt.prec, opt.tol, opt.max_iter, opt.scheme = prec, tol, max_iter, scheme
+    opt.prec, opt.tol, opt.max_iter, opt.scheme, opt.fused = prec, tol, max_iter, scheme, fused
     if pml is not None:
         cells, R0, order = pml
         keep.append(N.mm_pml((C.c_int32 * 6)(*cells), R0, order))
@@ -114,6 +114,7 @@ def _init(lib, n=(8, 4, 4), d=(1e-6,) * 3, dt=None, tol=1e-10, max_iter=10, prec
     dict(max_iter=0),
     dict(prec=7),
     dict(scheme=3),
+    dict(fused=2),
     dict(pml=((2, 2, 0, 0, 0, 0), 1e-6, 3), bc=(1, 0, 0)),     # layer on a periodic axis
     dict(pml=((4, 4, 0, 0, 0, 0), 1e-6, 3)),                  # layers fill the axis (8 cells)
     dict(pml=((2, 0, 0, 0, 0, 0), 1.5, 3)),                   # R0 >= 1

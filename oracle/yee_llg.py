@@ -155,8 +155,11 @@ def renormalise(m, Ms):
 
 
 def waveform(t, f0, Tp, t0):
-    """Gaussian-modulated sinusoid of the pulse equation in Sec. 5.2.1."""
-    return math.exp(-((t - t0) ** 2) / (2.0 * Tp * Tp)) * math.cos(2.0 * math.pi * f0 * t)
+    """Gaussian-modulated sinusoid of the pulse equation in Sec. 5.2.1.  The
+    square of t - t0 is the rounded product (a power through libm pow is not
+    always correctly rounded)."""
+    d = t - t0
+    return math.exp(-(d * d) / (2.0 * Tp * Tp)) * math.cos(2.0 * math.pi * f0 * t)
 
 
 # --------------------------------------------------------------------------

@@ -10,8 +10,9 @@ with the soft source, Step 3 H-M sub-step, probe sampling) on the
 advanced S untimed steps (default 600) so that the K timed steps fall in
 the part of the 1000-step run where the port pulse drives the ferrite and
 the H-M iteration takes its usual 2-3 iterations.  The FP64 run is the
-headline; the FP32 bulk mode runs the same workload afterwards and its
-fields are compared with the FP64 run's.  Prints one JSON line.
+headline; the FP32 bulk mode runs the same workload afterwards, and its
+error against the FP64 oracle is taken on the 1000-step crop run whose
+oracle results are stored in tests/golden.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -140,6 +141,29 @@ def write_traffic_record(pmc_dir, workload="filter512"):
 
 BULK_KERNELS = ("h_bulk", "h_far", "e_update")
 
+# Algorithmic HBM bytes per cell-step of the whole step (compulsory traffic of
+# the three phases, each reading its inputs once and writing its outputs
+# once, on the 3.1 %-magnetic filter grid): FP64 and FP32 bulk storage.
+STEP_BYTES_PER_CELL = {"fp64": 242.5, "fp32": 126.5}
+
+# profile class -> kernel name, per sub-step form
+_CLASS_NAMES_FUSED = {"hm_pre": "hm_fused", "hm_step": "hm_more", "h_bulk": "h_half"}
+
+
+def fused_form(kern, steps):
+    """The run took the fused H-M sub-step (one hm_fused and one hm_more per
+    sub-step, no hm_finish / hm_commit)."""
+    return kern["hm_finish"][1] == 0 and kern["hm_commit"][1] == 0 and kern["hm_pre"][1] == 2 * steps
+
+
+def hm_bytes_per_face(s):
+    """Algorithmic bytes per evolving magnetic face and sub-step of the H-M
+    iteration with its iterations fused: H^s read and H written (s each),
+    one E component read per face (three per cell), M^s read and M written
+    (24 B each, FP64), the face constants (Ms, alpha, gamma: 24 B per cell,
+    8 per face)."""
+    return 3 * s + 56
+
 
 def bytes_per_cell(kernel, s, tiles, cfg):
     """Algorithmic HBM bytes per cell for one launch of a bulk kernel with
@@ -164,6 +188,79 @@ def cells_per_launch(kernel, kern, tiles, cells, steps):
         return tiles["far_cells"]
     total = 2 * cells + (2 * steps - 2) * tiles["near_cells"]
     return total / max(1, kern["h_bulk"][1])
+
+
+def kernel_table(kern, info, cfg, s, steps):
+    """Per profile class: time per step, launches per step, average launch,
+    algorithmic bytes per launch and the achieved fraction of the HBM peak."""
+    tiles = info["tiles"]
+    cells = cfg.cells
+    fused = fused_form(kern, steps)
+    out = {}
+    for k, (ms, n) in kern.items():
+        if n == 0:
+            continue
+        name = _CLASS_NAMES_FUSED.get(k, k) if fused else k
+        row = {"ms_per_step": round(ms / steps, 4), "launches_per_step": round(n / steps, 3),
+               "avg_launch_ms": round(ms / n, 4)}
+        b = None
+        if k in BULK_KERNELS:
+            nc = cells_per_launch(k, kern, tiles, cells, steps)
+            row["cells_per_launch"] = nc if k != "h_bulk" else round(nc, 1)
+            b = bytes_per_cell(k, s, tiles, cfg) * nc
+        elif k == "hm_pre" and fused:
+            row["faces_per_launch"] = info["n_mag"]
+            b = hm_bytes_per_face(s) * info["n_mag"]
+        if b is not None:
+            gbs = b / (ms / n / 1e3) / 1e9
+            row.update({"algorithmic_bytes_per_launch": int(round(b)), "GB/s": round(gbs, 1),
+                        "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        out[name] = row
+    return out
+
+
+def fp32_vs_oracle():
+    """The 128 x 64 x 64 crop of the filter grid, 1000 steps, FP32 bulk mode,
+    against the FP64 oracle's stored run (tests/golden, written by a script
+    that runs the oracle alone): every probe series and integral, and E, H
+    and M - M0 on the stored sample of each field."""
+    import gzip
+    import paper_2103_12819_amd as mm
+    path = os.path.join(ROOT, "tests", "golden", "filter_crop_oracle.json.gz")
+    if not os.path.exists(path):
+        return None
+    gold = json.load(gzip.open(path, "rt"))
+    cfg = W.filter_crop(seed=0, steps=gold["steps"])
+    init = mm.from_config(cfg)
+    sim = mm.from_config(cfg, precision="fp32")
+    sim.step(cfg.steps)
+    errs = {}
+    groups = {"E": ("Ex", "Ey", "Ez"), "H": ("Hx", "Hy", "Hz"),
+              "M-M0": tuple("M" + f + c for f in "xyz" for c in "xyz")}
+    for gname, names in groups.items():
+        num = den = 0.0
+        for nm in names:
+            ref = gold["fields"][nm]
+            idx = np.array(ref["sample_idx"])
+            r = np.array([float.fromhex(v) for v in ref["sample"]])
+            got = sim.field(nm).reshape(-1)[idx]
+            if gname == "M-M0":
+                m0 = init.field(nm).reshape(-1)[idx]
+                r, got = r - m0, got - m0
+            num += float(np.sum((got - r) ** 2))
+            den += float(np.sum(r ** 2))
+        errs[gname] = float(f"{np.sqrt(num / den):.3e}")
+    for pid, p in enumerate(gold["probes"]):
+        r = np.array([float.fromhex(v) for v in p["series"]])
+        S_ref = float.fromhex(p["sum"])
+        sr, S = sim.probe(pid)
+        errs[f"probe{pid}"] = float(f"{np.linalg.norm(sr - r) / np.linalg.norm(r):.3e}")
+        errs[f"sum{pid}"] = float(f"{abs(S - S_ref) / max(abs(S_ref), cfg.dt * float(np.sum(np.abs(r)))):.3e}")
+    sim.close()
+    init.close()
+    return {"workload": "filter crop 128x64x64, 1000 steps (FP32 bulk, FP64 M and accumulators)",
+            "reference": "FP64 oracle, stored run", "fields_on": "512 stored samples per field",
+            "rel_l2": errs}
 
 
 def run_gpu(cfg, precision, steps, warmup, start):
@@ -443,18 +540,16 @@ def main():
     sim64, info64, ms64, wall64, kern64, it64 = run_gpu(cfg, "fp64", args.steps, args.warmup, args.start)
     per_step = ms64 / args.steps
     value = cells * args.steps / (ms64 / 1e3) / 1e6
-    # dominant kernel and its roofline
-    dom = max(BULK_KERNELS, key=lambda k: kern64[k][0])
-    dom_ms, dom_n = kern64[dom]
-    avg_s = dom_ms / dom_n / 1e3
-    dom_cells = cells_per_launch(dom, kern64, info64["tiles"], cells, args.steps)
-    algo_bytes = int(round(bytes_per_cell(dom, 8, info64["tiles"], cfg) * dom_cells))
-    achieved = algo_bytes / avg_s / 1e9
-    traffic = measured_traffic(dom, dom_cells)
+    table64 = kernel_table(kern64, info64, cfg, 8, args.steps)
+    # dominant kernel (largest share of the step, every class) and its roofline
+    dom = max(table64, key=lambda k: table64[k]["ms_per_step"])
+    d = table64[dom]
+    traffic = measured_traffic(dom, d.get("cells_per_launch")) if "cells_per_launch" in d else None
+    step_bytes = STEP_BYTES_PER_CELL["fp64"] * cells
     print(f"[bench] fp64 {per_step:.3f} ms/step, {value:.1f} Mcell/s, kernels {kern64}", flush=True)
 
     out = {
-        "metric": "coupled Mcell-updates/s (FP64; FP32 bulk mode alongside with its L2 error vs FP64)",
+        "metric": "coupled Mcell-updates/s (FP64; FP32 bulk mode alongside with its L2 error vs the FP64 oracle)",
         "value": round(value, 2),
         "unit": "Mcell-updates/s",
         "n_gpus": 1,
@@ -475,12 +570,17 @@ def main():
                           "note": "event pair around every kernel launch; kernel durations and roofline from here",
                           "iterations_per_substep": {str(k): int(v) for k, v in
                                                      zip(*np.unique(info64["profiled_iters"], return_counts=True))}},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "avg_launch_ms": round(avg_s * 1e3, 4),
-                     "algorithmic_bytes_per_launch": algo_bytes, "cells_per_launch": dom_cells},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GB/s"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["frac"],
+                     "traffic": traffic, "avg_launch_ms": d["avg_launch_ms"],
+                     "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"],
+                     "step": {"bytes_per_cell": STEP_BYTES_PER_CELL["fp64"],
+                              "algorithmic_bytes_per_step": int(step_bytes),
+                              "achieved": round(step_bytes / (per_step / 1e3) / 1e9, 1),
+                              "frac": round(step_bytes / (per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}},
         "tiles": info64["tiles"],
-        "kernels_fp64_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kern64.items()},
+        "kernels_fp64": table64,
+        "kernels_fp64_ms_per_step": {k: v["ms_per_step"] for k, v in table64.items()},
         "iterations_per_substep": {str(k): int(v) for k, v in
                                    zip(*np.unique(it64[-2 * args.steps:], return_counts=True))},
     }
@@ -488,15 +588,19 @@ def main():
         print("[bench] fp32 run", flush=True)
         sim32, info32, ms32, wall32, kern32, it32 = run_gpu(cfg, "fp32", args.steps, args.warmup, args.start)
         v32 = cells * args.steps / (ms32 / 1e3) / 1e6
-        l2 = {}
-        for nm in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):
-            a, b = sim32.field(nm), sim64.field(nm)
-            l2[nm] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
-        out["fp32"] = {"value": round(v32, 2), "ms_per_step": round(ms32 / args.steps, 4),
-                       "rel_l2_vs_fp64_after_steps": {k: float(f"{v:.3e}") for k, v in l2.items()},
-                       "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kern32.items()}}
-        print(f"[bench] fp32 {ms32 / args.steps:.3f} ms/step, {v32:.1f} Mcell/s", flush=True)
+        p32 = ms32 / args.steps
+        sb32 = STEP_BYTES_PER_CELL["fp32"] * cells
+        table32 = kernel_table(kern32, info32, cfg, 4, args.steps)
+        out["fp32"] = {"value": round(v32, 2), "ms_per_step": round(p32, 4),
+                       "roofline_step": {"bytes_per_cell": STEP_BYTES_PER_CELL["fp32"],
+                                         "achieved": round(sb32 / (p32 / 1e3) / 1e9, 1),
+                                         "frac": round(sb32 / (p32 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+                       "kernels": table32,
+                       "kernels_ms_per_step": {k: v["ms_per_step"] for k, v in table32.items()}}
+        print(f"[bench] fp32 {p32:.3f} ms/step, {v32:.1f} Mcell/s", flush=True)
         sim32.close()
+        print("[bench] fp32 error against the oracle (stored 1000-step crop run)", flush=True)
+        out["fp32"]["error_vs_fp64_oracle"] = fp32_vs_oracle()
     sim64.close()
     if not args.no_adjoint:
         print("[bench] adjoint cost (design128)", flush=True)

@@ -31,13 +31,17 @@ import numpy as np  # noqa: E402
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-KERNELS_H = os.path.join(ROOT, "paper_2103_12819_amd", "csrc", "kernels.h")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2103_12819_amd", "csrc", f) for f in ("kernels.h", "hm_fused.h")]
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 
 
 def _kernels_h_sha256():
+    """SHA-256 of the kernel sources (kernels.h, then hm_fused.h)."""
     import hashlib
-    return hashlib.sha256(open(KERNELS_H, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel, cells_per_launch):
@@ -53,7 +57,7 @@ def measured_traffic(kernel, cells_per_launch):
     if sha != rec.get("kernels_h_sha256"):
         return None
     k = rec.get("kernels", {}).get(kernel)
-    if k is None or k.get("cells_per_launch") != cells_per_launch:
+    if k is None or k.get("cells_per_launch", k.get("faces_per_launch")) != cells_per_launch:
         return None
     return k["traffic_bytes_per_launch"]
 
@@ -61,8 +65,9 @@ def measured_traffic(kernel, cells_per_launch):
 # kernel names in the counter databases -> the names used here (h_far is the
 # two-half-step instantiation of h_bulk)
 _PMC_NAMES = (("e_update", "e_update<double"), ("h_far", "h_bulk<double, false, 2>"),
-              ("h_bulk", "h_bulk<double, false, 1>"), ("hm_pre", "hm_pre<double"),
-              ("hm_step", "hm_step<double"), ("hm_finish", "hm_finish<double"),
+              ("h_bulk", "h_bulk<double, false, 1>"), ("h_half", "h_half_db<double"),
+              ("hm_fused", "hm_fused<double"), ("hm_more", "hm_more<double"),
+              ("hm_pre", "hm_pre<double"), ("hm_step", "hm_step<double"), ("hm_finish", "hm_finish<double"),
               ("hm_commit", "hm_commit<double"), ("probe_flux", "probe_flux<double"))
 
 
@@ -98,7 +103,8 @@ def write_traffic_record(pmc_dir, workload="filter512"):
         scale[ctr] = copy_bytes / (kib * 1024)
     cfg = W.CONFIGS[workload]()
     tiles = json.load(open(os.path.join(pmc_dir, "tiles.json")))
-    cells = {"e_update": cfg.cells, "h_far": tiles["far_cells"]}
+    cells = {"e_update": cfg.cells, "h_far": tiles["far_cells"], "h_half": tiles["near_cells"]}
+    faces = tiles.get("n_mag")
     fetch, write = one("FETCH_SIZE", "bench"), one("WRITE_SIZE", "bench")
     rec = {"kernels_h_sha256": _kernels_h_sha256(),
            "workload": f"{cfg.name} {cfg.n[0]}x{cfg.n[1]}x{cfg.n[2]} fp64",
@@ -123,9 +129,14 @@ def write_traffic_record(pmc_dir, workload="filter512"):
                "traffic_bytes_per_launch": int(rd + wr)}
         algo = "-"
         ratio = "-"
+        b = None
         if short in cells:
             ent["cells_per_launch"] = cells[short]
-            b = bytes_per_cell(short, 8, tiles, cfg) * cells[short]
+            b = bytes_per_cell("h_bulk" if short == "h_half" else short, 8, tiles, cfg) * cells[short]
+        elif short == "hm_fused" and faces:
+            ent["faces_per_launch"] = faces
+            b = hm_bytes_per_face(8) * faces
+        if b is not None:
             ent["algorithmic_bytes_per_launch"] = int(b)
             algo = f"{b / 1e9:.3f}"
             ratio = f"{(rd + wr) / b:.3f}"
@@ -529,7 +540,7 @@ def main():
     if args.tiles_json:
         import paper_2103_12819_amd as mm
         sim = mm.from_config(W.CONFIGS[args.workload](), with_probes=False)
-        json.dump(sim.tiles(), open(args.tiles_json, "w"))
+        json.dump(dict(sim.tiles(), n_mag=sim.info()["n_mag"]), open(args.tiles_json, "w"))
         sim.close()
         return
 
@@ -544,7 +555,7 @@ def main():
     # dominant kernel (largest share of the step, every class) and its roofline
     dom = max(table64, key=lambda k: table64[k]["ms_per_step"])
     d = table64[dom]
-    traffic = measured_traffic(dom, d.get("cells_per_launch")) if "cells_per_launch" in d else None
+    traffic = measured_traffic(dom, d.get("cells_per_launch", d.get("faces_per_launch")))
     step_bytes = STEP_BYTES_PER_CELL["fp64"] * cells
     print(f"[bench] fp64 {per_step:.3f} ms/step, {value:.1f} Mcell/s, kernels {kern64}", flush=True)
 

@@ -1157,9 +1157,11 @@ __global__ void probe_points(Geo g, Fields<T> F, Lag<T> L, const PointProbe* __r
   sums[q.slot] += dt * v;
 }
 
-// Poynting flux through the node plane x = i0: deterministic two-level sum
-// (fixed per-thread strides, a fixed tree per block, and the block partials
-// combined by the same fixed tree by whichever block finishes last).
+// Poynting flux through the node plane x = i0: deterministic two-level sum.
+// One thread per node (j, k) of the plane takes both terms there (E_y H_z
+// for j < ny, k < NZ and E_z H_y for j < NY, k < nz), so the lines of the
+// x-fastest arrays it touches serve both; a fixed tree per block, and the
+// block partials summed in a fixed order by whichever block finishes last.
 template <typename T>
 __global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, Lag<T> L, const int* __restrict__ planes,
                                                  const int* __restrict__ slots, double* __restrict__ partial,
@@ -1172,18 +1174,18 @@ __global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, Lag<T> L, 
   const bool pxp = g.per & 1;
   const int im = dn(i0, g.nx, pxp);
   const int nb = gridDim.x;
-  // Ey*Hz over j in [0,ny), k in [0,NZ); Ez*Hy over j in [0,NY), k in [0,nz)
-  const int n1 = g.ny * NZ, n2 = NY * g.nz;
   double s1 = 0.0, s2 = 0.0;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n1; e += nb * blockDim.x) {
-    const int k = e / g.ny, j = e - k * g.ny;
-    const double hz = 0.5 * (h_level(g, F, L, 2, im, j, k) + h_level(g, F, L, 2, i0, j, k));
-    s1 += D(F.E[1][at(g, i0, j, k)]) * hz;
-  }
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += nb * blockDim.x) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < NY * NZ) {
     const int k = e / NY, j = e - k * NY;
-    const double hy = 0.5 * (h_level(g, F, L, 1, im, j, k) + h_level(g, F, L, 1, i0, j, k));
-    s2 += D(F.E[2][at(g, i0, j, k)]) * hy;
+    if (j < g.ny) {
+      const double hz = 0.5 * (h_level(g, F, L, 2, im, j, k) + h_level(g, F, L, 2, i0, j, k));
+      s1 = D(F.E[1][at(g, i0, j, k)]) * hz;
+    }
+    if (k < g.nz) {
+      const double hy = 0.5 * (h_level(g, F, L, 1, im, j, k) + h_level(g, F, L, 1, i0, j, k));
+      s2 = D(F.E[2][at(g, i0, j, k)]) * hy;
+    }
   }
   __shared__ double r1[256], r2[256];
   __shared__ bool last;
@@ -1210,12 +1212,12 @@ __global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, Lag<T> L, 
   __syncthreads();
   if (!last) return;
   __threadfence();
-  // nb <= blockDim.x: one partial per thread, then the fixed tree
+  // thread t sums the partials t, t + 256, ... in order, then the fixed tree
   const double* pp = partial + (size_t)p * 2 * nb;
   double a = 0.0, b = 0.0;
-  if ((int)threadIdx.x < nb) {
-    a = __hip_atomic_load(&pp[2 * threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    b = __hip_atomic_load(&pp[2 * threadIdx.x + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+    a += __hip_atomic_load(&pp[2 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b += __hip_atomic_load(&pp[2 * q + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   r1[threadIdx.x] = a;
   r2[threadIdx.x] = b;

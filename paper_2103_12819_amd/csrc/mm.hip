@@ -477,7 +477,7 @@ mm_status freeze_probes(mm_ctx* c) {
     HIPCHECK(c, hipMemcpy(c->d_points, pts.data(), pts.size() * sizeof(mmk::PointProbe), hipMemcpyHostToDevice));
   }
   if (c->nflux) {
-    c->flux_blocks = 256;
+    c->flux_blocks = (nodes(c, 1) * nodes(c, 2) + 255) / 256;   // one thread per node of the plane
     c->d_planes = (int*)dalloc(c, planes.size() * sizeof(int));
     c->d_slots = (int*)dalloc(c, slots.size() * sizeof(int));
     c->d_partial = (double*)dalloc(c, (size_t)c->nflux * 2 * c->flux_blocks * sizeof(double));

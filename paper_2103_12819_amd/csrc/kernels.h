@@ -30,6 +30,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 // Threads per block of the magnetic-face kernels (hm_pre, hm_step,
 // hm_commit) and the cap on their blocks per CU: the grid of those launches
@@ -312,17 +313,64 @@ __global__ __launch_bounds__(64 * RY) void e_update(Geo g, T* __restrict__ Ex, T
 // hold no magnetic face and no face an H_eff of a magnetic face reads, the
 // two passes fuse into one.  Each half step is the same rounded
 // subtraction, so the result equals two NP = 1 launches bit for bit.
+//
+// With NP = 2 the pass also passes through H^{n+1}, the level the probes
+// sample.  For up to kCapPlanes flux planes x = i0 it stores what the
+// Poynting flux (Sec. 5.2) needs from these tiles densely per plane node
+// (j, k): E_y, E_z at i0 and H_y, H_z at i0 - 1 and i0 at level n+1, so the
+// probe reads a few contiguous arrays instead of one cache line per value
+// of x-fastest fields.
 // ---------------------------------------------------------------------------
+constexpr int kCapPlanes = 4;
+constexpr int kCapPlanesZ = 32;   // tile depth the capture allows
+template <typename T>
+struct FluxCap {
+  T* buf;                  // [plane][6][NY][NZ]: Ey(i0), Ez(i0), Hy(im), Hz(im), Hy(i0), Hz(i0); null: off
+  int n;                   // planes captured (distinct x)
+  int i0[kCapPlanes];      // plane x node
+  int im[kCapPlanes];      // the x face before it (wrapped on a periodic x axis)
+  int NZ;                  // plane nodes along z
+  long long nn;            // plane nodes, NY * NZ
+};
+
 template <typename T, bool MU, int NP>
 __global__ __launch_bounds__(256) void h_bulk(Geo g, T* __restrict__ Hx, T* __restrict__ Hy,
                                              T* __restrict__ Hz, const T* __restrict__ Ex,
                                              const T* __restrict__ Ey, const T* __restrict__ Ez,
-                                             const T* __restrict__ mu, T coef0, T h, Tiles tl) {
+                                             const T* __restrict__ mu, T coef0, T h, Tiles tl,
+                                             FluxCap<T> cap = {}) {
   int i, j, k0, k1;
   tile_span(tl, g.nz, i, j, k0, k1);
+  const int tx = i;
   i += threadIdx.x;
   j += threadIdx.y;
-  if (i >= g.nx || j >= g.ny || k0 >= k1) return;
+  // flux-plane capture roles of this wave (one x row of 64 at one j): the
+  // lane whose column is x = i0 of a plane and the lane whose column is its
+  // x = im, with the offsets of node (j, k0) in that plane's capture; all
+  // wave-uniform.  During the march the capture lanes park their values in
+  // LDS (no global store inside the pipelined loop); afterwards the wave
+  // writes them out, one lane per plane (tiles of at most kCapPlanesZ planes).
+  __shared__ T stash[NP == 2 ? 4 * 6 * kCapPlanesZ : 1];
+  int l0 = -1, lm = -1;
+  long long o0 = 0, om = 0;
+  if (NP == 2 && cap.buf) {
+    const long long jw = __builtin_amdgcn_readfirstlane(j);
+    for (int p = 0; p < cap.n; ++p) {
+      const long long b = (long long)p * 6 * cap.nn + jw * cap.NZ + k0;
+      if (cap.i0[p] >= tx && cap.i0[p] < tx + 64) {
+        l0 = cap.i0[p] - tx;
+        o0 = b;
+      }
+      if (cap.im[p] >= tx && cap.im[p] < tx + 64) {
+        lm = cap.im[p] - tx;
+        om = b + 2 * cap.nn;
+      }
+    }
+  }
+  if (j >= g.ny || k0 >= k1) return;
+  const bool capw = NP == 2 && (l0 >= 0 || lm >= 0);   // wave-uniform
+  T* st = stash + (NP == 2 ? __builtin_amdgcn_readfirstlane(threadIdx.y) * 6 * kCapPlanesZ : 0);
+  if (i < g.nx) {
   const bool pxp = g.per & 1, pyp = g.per & 2, pzp = g.per & 4;
   const bool iin = pxp || i >= 1;
   const bool jin = pyp || j >= 1;
@@ -368,6 +416,7 @@ __global__ __launch_bounds__(256) void h_bulk(Geo g, T* __restrict__ Hx, T* __re
     if (k + 1 < k1) load(k + 1, nxt);
     __builtin_amdgcn_sched_barrier(0);
     const int c = at(g, i, j, k);
+    T hy1 = cur.hy, hz1 = cur.hz;   // level n+1, after the first half step
     if (iin) {
       const T curl = dq(cur.ez_jp - cur.ez, sdy, idy) - dq(cur.ey_kp - ey_k, sdz, idz);
       const T cf = MU ? h / (mu0 * (half * (cur.mu_im + cur.mu_c))) : coef0;
@@ -378,20 +427,55 @@ __global__ __launch_bounds__(256) void h_bulk(Geo g, T* __restrict__ Hx, T* __re
     if (jin) {
       const T curl = dq(cur.ex_kp - ex_k, sdz, idz) - dq(cur.ez_ip - cur.ez, sdx, idx);
       const T cf = MU ? h / (mu0 * (half * (cur.mu_jm + cur.mu_c))) : coef0;
-      T v = cur.hy;
-      for (int p = 0; p < NP; ++p) v = v - cf * curl;
+      T v = cur.hy - cf * curl;
+      hy1 = v;
+      for (int p = 1; p < NP; ++p) v = v - cf * curl;
       Hy[c] = v;
     }
     if (pzp || k >= 1) {
       const T curl = dq(cur.ey_ip - ey_k, sdx, idx) - dq(cur.ex_jp - ex_k, sdy, idy);
       const T cf = MU ? h / (mu0 * (half * (mu_km + cur.mu_c))) : coef0;
-      T v = cur.hz;
-      for (int p = 0; p < NP; ++p) v = v - cf * curl;
+      T v = cur.hz - cf * curl;
+      hz1 = v;
+      for (int p = 1; p < NP; ++p) v = v - cf * curl;
       Hz[c] = v;
+    }
+    if (capw) {   // capture: E and H at level n+1
+      const int kk = k - k0;
+      if ((int)threadIdx.x == l0) {
+        st[kk] = ey_k;
+        st[kCapPlanesZ + kk] = cur.ez;
+        st[4 * kCapPlanesZ + kk] = hy1;
+        st[5 * kCapPlanesZ + kk] = hz1;
+      }
+      if ((int)threadIdx.x == lm) {
+        st[2 * kCapPlanesZ + kk] = hy1;
+        st[3 * kCapPlanesZ + kk] = hz1;
+      }
     }
     ex_k = cur.ex_kp;
     ey_k = cur.ey_kp;
     if (MU) mu_km = cur.mu_c;
+  }
+  }
+  if (capw) {
+    // the LDS writes above came from other lanes of this wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int kk = threadIdx.x;   // node (j, k0 + kk); consecutive lanes, consecutive addresses
+    if (kk < k1 - k0) {
+      if (l0 >= 0) {
+        cap.buf[o0 + kk] = st[kk];
+        cap.buf[o0 + cap.nn + kk] = st[kCapPlanesZ + kk];
+        cap.buf[o0 + 4 * cap.nn + kk] = st[4 * kCapPlanesZ + kk];
+        cap.buf[o0 + 5 * cap.nn + kk] = st[5 * kCapPlanesZ + kk];
+      }
+      if (lm >= 0) {
+        cap.buf[om + kk] = st[2 * kCapPlanesZ + kk];
+        cap.buf[om + cap.nn + kk] = st[3 * kCapPlanesZ + kk];
+      }
+    }
   }
 }
 
@@ -1158,17 +1242,22 @@ __global__ void probe_points(Geo g, Fields<T> F, Lag<T> L, const PointProbe* __r
 }
 
 // Poynting flux through the node plane x = i0: deterministic two-level sum.
-// One thread per node (j, k) of the plane takes both terms there (E_y H_z
+// One thread per node (j, k) of the plane, z fastest, takes both terms there (E_y H_z
 // for j < ny, k < NZ and E_z H_y for j < NY, k < nz), so the lines of the
 // x-fastest arrays it touches serve both; a fixed tree per block, and the
 // block partials summed in a fixed order by whichever block finishes last.
+//
+// With a capture (FluxCap.buf set; the far tiles' fused pass has run and
+// holds H^{n+3/2}), values at faces and edges of far tiles come from the
+// capture that pass stored on its way through level n+1; the near tiles'
+// values are read from the fields as without one.
 template <typename T>
 __global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, Lag<T> L, const int* __restrict__ planes,
                                                  const int* __restrict__ slots, double* __restrict__ partial,
                                                  unsigned int* __restrict__ ticket,
                                                  double* __restrict__ series, size_t cap,
                                                  double* __restrict__ sums, long step, double dt,
-                                                 double dydz, int NY, int NZ) {
+                                                 double dydz, int NY, int NZ, FluxCap<T> fc) {
   const int p = blockIdx.y;
   const int i0 = planes[p];
   const bool pxp = g.per & 1;
@@ -1177,14 +1266,24 @@ __global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, Lag<T> L, 
   double s1 = 0.0, s2 = 0.0;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < NY * NZ) {
-    const int k = e / NY, j = e - k * NY;
+    const int j = e / NZ, k = e - j * NZ;
+    const T* cb = fc.buf ? fc.buf + (long long)p * 6 * fc.nn + e : nullptr;
+    // far tile at (i, j, k): the capture holds the value there
+    auto captured = [&](int i) {
+      return cb && i < g.nx && j < g.ny && k < g.nz && L.far[(i >> 6) + L.gx * ((j >> 2) + L.gy * (k / L.kc))];
+    };
+    const bool c0 = captured(i0), cm = captured(im);
     if (j < g.ny) {
-      const double hz = 0.5 * (h_level(g, F, L, 2, im, j, k) + h_level(g, F, L, 2, i0, j, k));
-      s1 = D(F.E[1][at(g, i0, j, k)]) * hz;
+      const double hzm = cm ? D(cb[3 * fc.nn]) : h_level(g, F, L, 2, im, j, k);
+      const double hz0 = c0 ? D(cb[5 * fc.nn]) : h_level(g, F, L, 2, i0, j, k);
+      const double hz = 0.5 * (hzm + hz0);
+      s1 = (c0 ? D(cb[0]) : D(F.E[1][at(g, i0, j, k)])) * hz;
     }
     if (k < g.nz) {
-      const double hy = 0.5 * (h_level(g, F, L, 1, im, j, k) + h_level(g, F, L, 1, i0, j, k));
-      s2 = D(F.E[2][at(g, i0, j, k)]) * hy;
+      const double hym = cm ? D(cb[2 * fc.nn]) : h_level(g, F, L, 1, im, j, k);
+      const double hy0 = c0 ? D(cb[4 * fc.nn]) : h_level(g, F, L, 1, i0, j, k);
+      const double hy = 0.5 * (hym + hy0);
+      s2 = (c0 ? D(cb[fc.nn]) : D(F.E[2][at(g, i0, j, k)])) * hy;
     }
   }
   __shared__ double r1[256], r2[256];

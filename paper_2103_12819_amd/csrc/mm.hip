@@ -167,6 +167,7 @@ struct mm_ctx {
   double* d_partial;
   unsigned int* d_ticket;
   int flux_blocks;
+  void* d_fcap;           // flux-plane capture of the far tiles' fused pass, or null
   bool probes_frozen;
 
   long step;
@@ -487,6 +488,19 @@ mm_status freeze_probes(mm_ctx* c) {
     HIPCHECK(c, hipMemcpy(c->d_planes, planes.data(), planes.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(c->d_slots, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemset(c->d_ticket, 0, (size_t)c->nflux * sizeof(unsigned int)));
+    // the far tiles' pass stores at most one plane per 64-column tile row
+    // and role (x = i0, x = im)
+    bool fcap = c->nflux <= mmk::kCapPlanes;
+    for (int p = 0; p < c->nflux && fcap; ++p)
+      for (int q = 0; q < p; ++q) {
+        const int ip = planes[p], iq = planes[q];
+        const int mp = (c->per & 1) && ip == 0 ? c->nx - 1 : ip - 1, mq = (c->per & 1) && iq == 0 ? c->nx - 1 : iq - 1;
+        if (ip / 64 == iq / 64 || mp / 64 == mq / 64) fcap = false;
+      }
+    if (fcap) {
+      c->d_fcap = dalloc(c, (size_t)c->nflux * 6 * nodes(c, 1) * nodes(c, 2) * c->esz);
+      if (!c->d_fcap) return fail(c, MM_ENOMEM, "probe allocation failed");
+    }
   }
   return MM_OK;
 }
@@ -905,29 +919,57 @@ mm_status e_step(mm_ctx* c) {
 
 // The fused Faraday pass of the far tiles: Step 3 of step n and Step 1 of
 // step n+1 (both with curl E^{n+1}), H^{n+1/2} -> H^{n+3/2}.
+// The capture descriptor of the flux planes (buf null: none).
 template <typename T>
-mm_status h_far(mm_ctx* c) {
+mmk::FluxCap<T> flux_cap(const mm_ctx* c, bool on) {
+  mmk::FluxCap<T> fc{};
+  if (!on) return fc;
+  std::vector<int> planes;
+  for (const ProbeRec& r : c->probes)
+    if (r.d.kind != 0) planes.push_back(r.d.i);
+  fc.buf = (T*)c->d_fcap;
+  fc.n = (int)planes.size();
+  for (int p = 0; p < fc.n; ++p) {
+    fc.i0[p] = planes[p];
+    fc.im[p] = (c->per & 1) && planes[p] == 0 ? c->nx - 1 : planes[p] - 1;
+  }
+  fc.NZ = nodes(c, 2);
+  fc.nn = (long long)nodes(c, 1) * fc.NZ;
+  return fc;
+}
+
+// Whether the far tiles' fused pass stores the flux planes' values (the flux
+// probe then runs after it).
+bool flux_captured(const mm_ctx* c) {
+  return c->d_fcap && c->n_far > 0 && c->tkc <= mmk::kCapPlanesZ && !c->adj_recompute;
+}
+
+template <typename T>
+mm_status h_far(mm_ctx* c, bool cap = false) {
   if (c->n_far == 0) return MM_OK;
   const Geo g = make_geo(c);
   const mmk::Tiles tl = tiles(c, c->d_tl_far);
   const double h = 0.5 * c->dt, hmu0 = h / mmk::kMu0;
+  const mmk::FluxCap<T> fc = flux_cap<T>(c, cap);
   Timed tm(c, 7);
   if (c->mu)
     hipLaunchKernelGGL((mmk::h_bulk<T, true, 2>), dim3(c->n_far), dim3(64, 4), 0, c->stream, g, (T*)c->H[0],
                        (T*)c->H[1], (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2],
-                       (const T*)c->mu, (T)hmu0, (T)h, tl);
+                       (const T*)c->mu, (T)hmu0, (T)h, tl, fc);
   else
     hipLaunchKernelGGL((mmk::h_bulk<T, false, 2>), dim3(c->n_far), dim3(64, 4), 0, c->stream, g, (T*)c->H[0],
                        (T*)c->H[1], (T*)c->H[2], (const T*)c->E[0], (const T*)c->E[1], (const T*)c->E[2],
-                       (const T*)c->mu, (T)hmu0, (T)h, tl);
+                       (const T*)c->mu, (T)hmu0, (T)h, tl, fc);
   HIPCHECK(c, hipGetLastError());
   return MM_OK;
 }
 
 // Probe sampling at level c->step + 1.
 // lagged: the far tiles hold H^{n+1/2} (the fused pass comes after).
+// which: 1 point probes, 2 flux planes, 3 both.  captured: the far tiles'
+// fused pass has run with the flux-plane capture (the flux planes only).
 template <typename T>
-mm_status record_probes(mm_ctx* c, bool lagged = false) {
+mm_status record_probes(mm_ctx* c, bool lagged = false, int which = 3, bool captured = false) {
   if (c->adj_recompute) return MM_OK;
   const Geo g = make_geo(c);
   const mmk::Fields<T> F = make_fields<T>(c);
@@ -940,15 +982,16 @@ mm_status record_probes(mm_ctx* c, bool lagged = false) {
   L.gx = c->tgx;
   L.gy = c->tgy;
   L.kc = c->tkc;
+  if (!(which & 1 ? c->npoints : 0) && !(which & 2 ? c->nflux : 0)) return MM_OK;
   Timed tm(c, 5);
-  if (c->npoints)
+  if ((which & 1) && c->npoints)
     hipLaunchKernelGGL((mmk::probe_points<T>), dim3((c->npoints + 63) / 64), dim3(64), 0, c->stream, g, F, L,
                        c->d_points, c->npoints, c->d_series, c->series_cap, c->d_sums, c->step, c->dt);
-  if (c->nflux) {
+  if ((which & 2) && c->nflux) {
     const int NY = nodes(c, 1), NZ = nodes(c, 2);
     hipLaunchKernelGGL((mmk::probe_flux<T>), dim3(c->flux_blocks, c->nflux), dim3(256), 0, c->stream, g, F, L,
                        c->d_planes, c->d_slots, c->d_partial, c->d_ticket, c->d_series, c->series_cap,
-                       c->d_sums, c->step, c->dt, c->dy * c->dz, NY, NZ);
+                       c->d_sums, c->step, c->dt, c->dy * c->dz, NY, NZ, flux_cap<T>(c, captured));
   }
   HIPCHECK(c, hipGetLastError());
   return MM_OK;
@@ -1021,8 +1064,10 @@ mm_status run_steps(mm_ctx* c, int64_t n) {
       if ((s = copy_near<T>(c, false))) return s;
       c->chain_fused = false;
     }
-    if ((s = record_probes<T>(c, !end))) return s;
-    if (!end && (s = h_far<T>(c))) return s;
+    const bool cap = !end && c->nflux && flux_captured(c);
+    if ((s = record_probes<T>(c, !end, cap ? 1 : 3))) return s;
+    if (!end && (s = h_far<T>(c, cap))) return s;
+    if (cap && (s = record_probes<T>(c, true, 2, true))) return s;
     lagging = !end;
     c->step++;
   }

@@ -382,7 +382,8 @@ def air_waveguide(steps: int = 80000, pml_cells: int = 64, source: str = "soft")
     return cfg
 
 
-def tunable_filter(steps: int = 320000, pml_cells: int = 64, gap: int = 16, n=(1024, 4, 512)) -> Config:
+def tunable_filter(steps: int = 320000, pml_cells: int = 64, gap: int = 16, n=(1024, 4, 512),
+                   source: str = "surface") -> Config:
     """The magnetically tunable filter of Sec. 5.2.2: the waveguide of
     air_waveguide() with a YIG slab 0.45 mm thick against the x = 0 side
     wall, over the full height and along the guide (Ms = 1.3926e5 A/m,
@@ -390,7 +391,11 @@ def tunable_filter(steps: int = 320000, pml_cells: int = 64, gap: int = 16, n=(1
     1024 x 4 x 512 cells, CFL 0.8.  The slab stops `gap` cells short of the
     open layer at z = -L/2 (magnetic material inside the layer is not
     supported).  320,000 steps are 12.5 ns, four decay times of the damped
-    precession (1 / (alpha omega) ~ 3 ns): the spectrum has settled."""
+    precession (1 / (alpha omega) ~ 3 ns): the spectrum has settled.
+    Drive as in air_waveguide(): "surface", the paper's surface current on
+    the PEC end (the held wall faces may not be magnetic, so the slab's
+    magnetisation stops one cell short of that end; its permittivity does
+    not), or "soft", the current sheet one cell inside it."""
     W_, h_, L_ = 14.95e-3, 10.16e-3, 500e-3
     d = (W_ / n[0], h_ / n[1], L_ / n[2])
     cfg = Config(name="mtf", n=n, d=d, dt=cfl_dt(0.8, *d), steps=steps)
@@ -412,9 +417,17 @@ def tunable_filter(steps: int = 320000, pml_cells: int = 64, gap: int = 16, n=(1
     cfg.tol = 1e-10
     prof = np.zeros(edge_shape(n, (False,) * 3, 1))
     xi = np.arange(n[0] + 1) * d[0]
-    prof[n[2] - 1, :, :] = np.sin(np.pi * xi / W_)[None, :]
     f0 = 10.5e9
-    cfg.source = Source(1, prof, f0, 1.0 / f0, 3.0 / f0)
+    if source == "soft":
+        prof[n[2] - 1, :, :] = np.sin(np.pi * xi / W_)[None, :]
+        cfg.source = Source(1, prof, f0, 1.0 / f0, 3.0 / f0)
+    elif source == "surface":
+        prof[n[2], :, :] = np.sin(np.pi * xi / W_)[None, :]
+        cfg.surface_currents = [SurfaceCurrent(2, 1, 1, prof, f0, 1.0 / f0, 3.0 / f0)]
+        Ms[-1] = 0.0
+        alpha[-1] = 0.0
+    else:
+        raise ValueError(source)
     cfg.pml = ((0, 0, 0, 0, pml_cells, 0), 1e-6, 3.0)
     cfg.probes = [Probe(0, FIELD_ID["Ey"], n[0] // 2, n[1] // 2, k) for k in range(n[2] + 1)]
     return cfg

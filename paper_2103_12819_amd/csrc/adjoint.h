@@ -367,6 +367,25 @@ __global__ __launch_bounds__(256) void add_curl_h(Geo g, T* __restrict__ Eb0, T*
   }
 }
 
+// Several device-to-device copies in one launch (the per-step state saves of
+// the recompute): array blockIdx.y, 8-byte words, grid-stride over x.
+constexpr int kCopyMax = 9;
+struct CopyBatch {
+  const unsigned long long* src[kCopyMax];
+  unsigned long long* dst[kCopyMax];
+  unsigned long long words[kCopyMax];
+};
+
+__global__ __launch_bounds__(256) void copy_batch(CopyBatch b) {
+  const int a = blockIdx.y;
+  const unsigned long long n = b.words[a];
+  const unsigned long long* __restrict__ s = b.src[a];
+  unsigned long long* __restrict__ d = b.dst[a];
+  for (unsigned long long q = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (unsigned long long)gridDim.x * blockDim.x)
+    d[q] = s[q];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void zero_touched(const int* __restrict__ tidx,
                                                    const unsigned char* __restrict__ tfam, int nt, T* Xb0,

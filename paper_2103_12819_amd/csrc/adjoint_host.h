@@ -41,24 +41,61 @@ size_t state_bytes(const mm_ctx* c) {
   return 6 * c->nelem * c->esz + 3 * (c->h_idx.size() ? c->h_idx.size() : 1) * sizeof(double);
 }
 
-// state block layout: E0 E1 E2 H0 H1 H2 (nelem * esz each), M0 M1 M2 (ntot doubles each)
-mm_status copy_state(mm_ctx* c, void* blk, bool save) {
+// Copies (dst[q] <- src[q], bytes[q], multiples of 8) in one launch.
+struct CopyList {
+  int n = 0;
+  const void* src[mmk::kCopyMax];
+  void* dst[mmk::kCopyMax];
+  size_t bytes[mmk::kCopyMax];
+  void add(const void* s, void* d, size_t b) {
+    src[n] = s;
+    dst[n] = d;
+    bytes[n] = b;
+    ++n;
+  }
+};
+
+mm_status run_copies(mm_ctx* c, const CopyList& L) {
+  if (L.n == 0) return MM_OK;
+  mmk::CopyBatch b;
+  std::memset(&b, 0, sizeof b);
+  size_t most = 0;
+  for (int q = 0; q < L.n; ++q) {
+    b.src[q] = (const unsigned long long*)L.src[q];
+    b.dst[q] = (unsigned long long*)L.dst[q];
+    b.words[q] = L.bytes[q] / 8;
+    most = std::max(most, L.bytes[q] / 8);
+  }
+  const unsigned gx = (unsigned)std::max<size_t>(1, std::min<size_t>((most + 1023) / 1024, 2048));
+  hipLaunchKernelGGL(mmk::copy_batch, dim3(gx, L.n), dim3(256), 0, c->stream, b);
+  HIPCHECK(c, hipGetLastError());
+  return MM_OK;
+}
+
+// E, H and M to (save) or from a block laid out as E0 E1 E2 H0 H1 H2
+// (nelem * esz each), M0 M1 M2 (ntot doubles each), added to a copy list.
+void add_state(const mm_ctx* c, CopyList& L, void* blk, bool save) {
   const size_t fb = c->nelem * c->esz;
   const size_t ntot = c->h_idx.size();
   char* p = (char*)blk;
   for (int a = 0; a < 3; ++a) {
     void* e = p + a * fb;
     void* h = p + (3 + a) * fb;
-    HIPCHECK(c, hipMemcpyAsync(save ? e : c->E[a], save ? c->E[a] : e, fb, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHECK(c, hipMemcpyAsync(save ? h : c->H[a], save ? c->H[a] : h, fb, hipMemcpyDeviceToDevice, c->stream));
+    L.add(save ? c->E[a] : e, save ? e : c->E[a], fb);
+    L.add(save ? c->H[a] : h, save ? h : c->H[a], fb);
   }
   if (ntot)
     for (int a = 0; a < 3; ++a) {
       void* m = p + 6 * fb + a * ntot * sizeof(double);
-      HIPCHECK(c, hipMemcpyAsync(save ? m : (void*)c->d_M[a], save ? (void*)c->d_M[a] : m, ntot * sizeof(double),
-                                 hipMemcpyDeviceToDevice, c->stream));
+      L.add(save ? (void*)c->d_M[a] : m, save ? m : (void*)c->d_M[a], ntot * sizeof(double));
     }
-  return MM_OK;
+}
+
+// state block layout: see add_state
+mm_status copy_state(mm_ctx* c, void* blk, bool save) {
+  CopyList L;
+  add_state(c, L, blk, save);
+  return run_copies(c, L);
 }
 
 mm_status save_checkpoint(mm_ctx* c, size_t idx) {
@@ -70,23 +107,20 @@ mm_status save_checkpoint(mm_ctx* c, size_t idx) {
   return copy_state(c, c->ckpts[idx], true);
 }
 
-// copy 3 field arrays (E or H) to / from a packed block of 3 arrays
-mm_status copy3(mm_ctx* c, void* blk, void* const* arr, bool save) {
+// 3 field arrays (E or H) to / from a packed block of 3 arrays
+void add3(const mm_ctx* c, CopyList& L, void* blk, void* const* arr, bool save) {
   const size_t fb = c->nelem * c->esz;
   for (int a = 0; a < 3; ++a) {
     void* q = (char*)blk + a * fb;
-    HIPCHECK(c, hipMemcpyAsync(save ? q : arr[a], save ? arr[a] : q, fb, hipMemcpyDeviceToDevice, c->stream));
+    L.add(save ? arr[a] : q, save ? q : arr[a], fb);
   }
-  return MM_OK;
 }
 
-mm_status copyM(mm_ctx* c, double* blk, bool save) {
+void addM(const mm_ctx* c, CopyList& L, double* blk, bool save) {
   const size_t ntot = c->h_idx.size();
   for (int a = 0; a < 3 && ntot; ++a)
-    HIPCHECK(c, hipMemcpyAsync(save ? (void*)(blk + a * ntot) : (void*)c->d_M[a],
-                               save ? (void*)c->d_M[a] : (void*)(blk + a * ntot), ntot * sizeof(double),
-                               hipMemcpyDeviceToDevice, c->stream));
-  return MM_OK;
+    L.add(save ? (void*)c->d_M[a] : (void*)(blk + a * ntot), save ? (void*)(blk + a * ntot) : (void*)c->d_M[a],
+          ntot * sizeof(double));
 }
 
 // Faces that evolving magnetic faces read (themselves and their 8
@@ -379,11 +413,21 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
   c->substep = (int)(2 * m0);
   c->adj_recompute = true;
   for (int j = 0; j < len; ++j) {
-    if ((s = copy3(c, w.sE[j], c->E, true)) || (s = copy3(c, w.sH[j], c->H, true)) || (s = copyM(c, w.sM[j], true)))
-      return s;
+    {
+      CopyList L;
+      add3(c, L, w.sE[j], c->E, true);
+      add3(c, L, w.sH[j], c->H, true);
+      addM(c, L, w.sM[j], true);
+      if ((s = run_copies(c, L))) return s;
+    }
     c->hlog_cur = w.slog[j];
     if ((s = substep<T>(c))) return s;
-    if ((s = copy3(c, w.sHh[j], c->H, true)) || (s = copyM(c, w.sMh[j], true))) return s;
+    {
+      CopyList L;
+      add3(c, L, w.sHh[j], c->H, true);
+      addM(c, L, w.sMh[j], true);
+      if ((s = run_copies(c, L))) return s;
+    }
     if ((s = e_step<T>(c))) return s;
     c->hlog_cur = w.slog[j] + lsub;
     if ((s = substep<T>(c))) return s;

@@ -502,13 +502,18 @@ mm_status adjoint_run(mm_ctx* c, int i0, double* grad_eps, double* grad_Ms) {
       c->substep = (int)(2 * n0);
       c->adj_recompute = true;
       c->hlog_cur = nullptr;
-      const long last = n0 + (nsp - 1) * K2;
-      while (c->step < last) {
-        if ((s = substep<T>(c)) || (s = e_step<T>(c)) || (s = substep<T>(c))) return s;
-        c->step++;
-        if ((c->step - n0) % K2 == 0 && (s = copy_state(c, w.ick[(c->step - n0) / K2 - 1], true))) return s;
+      // nothing is stored per step here, so the spans run as the forward ran
+      // them (far tiles' fused pass, fused H-M sub-step; the same bits), each
+      // ending at an integer level for its inner checkpoint
+      const long keep = c->ckpt_every;
+      c->ckpt_every = 0;
+      for (long q = 1; q < nsp && !s; ++q) {
+        s = run_steps<T>(c, K2);
+        if (!s) s = copy_state(c, w.ick[q - 1], true);
       }
+      c->ckpt_every = keep;
       c->adj_recompute = false;
+      if (s) return s;
     }
     for (long q = nsp - 1; q >= 0; --q) {
       const long m0 = n0 + q * K2, m1 = std::min<long>(n1, m0 + K2);

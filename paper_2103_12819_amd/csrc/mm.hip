@@ -1036,7 +1036,8 @@ mm_status copy_near(mm_ctx* c, bool to_shadow) {
 
 // Whether the next run of steps takes the fused sub-step.
 bool fused_for_chain(const mm_ctx* c) {
-  if (!c->fused_ok || c->adj_recompute || c->hlog_cur) return false;
+  // (the adjoint's first recompute, which logs no iterates, may take it)
+  if (!c->fused_ok || c->hlog_cur) return false;
   if (c->fixed_iter > mmk::kFMaxK) return false;
   for (const HardSrc& hs : c->hard)
     if (hs.field >= 3) return false;

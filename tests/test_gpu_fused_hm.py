@@ -184,15 +184,18 @@ def test_nonconvergence_and_nonfinite_are_reported():
     assert ei.value.status == -5
 
 
-def test_adjoint_with_a_fused_forward_run():
-    """The adjoint recomputes its segments with the per-iteration launches;
-    with a fused forward run its gradients are the same bits."""
+@pytest.mark.parametrize("inner", [0, 3])
+def test_adjoint_with_a_fused_forward_run(inner):
+    """The adjoint recomputes the steps it reverses with the per-iteration
+    launches (they log every iterate); with two-level checkpoints its first
+    recompute, which only lays down the inner checkpoints, runs the chained
+    forward form, fused here.  Either way the gradients are the same bits."""
     mm = _mm()
     cfg = W.design128(seed=0, steps=30, n=(32, 16, 8))
     out = []
     for fz in (1, -1):
         sim = mm.from_config(cfg, fused=fz)
-        sim.enable_adjoint(10, 0)
+        sim.enable_adjoint(10, inner)
         sim.step(cfg.steps)
         out.append(sim.adjoint(0))
         sim.close()

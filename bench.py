@@ -510,7 +510,7 @@ def main():
         write_traffic_record(args.traffic_record, args.workload)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU slab decomposition is described in the design notes only)",
               file=sys.stderr)
         sys.exit(2)

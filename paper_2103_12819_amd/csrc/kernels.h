@@ -1242,22 +1242,23 @@ __global__ void probe_points(Geo g, Fields<T> F, Lag<T> L, const PointProbe* __r
 }
 
 // Poynting flux through the node plane x = i0: deterministic two-level sum.
-// One thread per node (j, k) of the plane, z fastest, takes both terms there (E_y H_z
-// for j < ny, k < NZ and E_z H_y for j < NY, k < nz), so the lines of the
-// x-fastest arrays it touches serve both; a fixed tree per block, and the
-// block partials summed in a fixed order by whichever block finishes last.
+// One thread per node (j, k) of the plane, z fastest, takes both terms there
+// (E_y H_z for j < ny, k < NZ and E_z H_y for j < NY, k < nz), so the lines
+// of the x-fastest arrays it touches serve both; a fixed tree per block into
+// one partial per block, and probe_flux_sum adds the partials in a fixed
+// order (a launch of its own: a last-block ticket needed a device-scope
+// fence per block, which cost more than the launch).
 //
 // With a capture (FluxCap.buf set; the far tiles' fused pass has run and
 // holds H^{n+3/2}), values at faces and edges of far tiles come from the
 // capture that pass stored on its way through level n+1; the near tiles'
-// values are read from the fields as without one.
+// values are read from the fields as without one.  fmask (per plane node,
+// bit 0: the node's x = i0 entries lie in a far tile, bit 1: its x = im
+// entries) says which; it is fixed by the tile split.
 template <typename T>
 __global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, Lag<T> L, const int* __restrict__ planes,
-                                                 const int* __restrict__ slots, double* __restrict__ partial,
-                                                 unsigned int* __restrict__ ticket,
-                                                 double* __restrict__ series, size_t cap,
-                                                 double* __restrict__ sums, long step, double dt,
-                                                 double dydz, int NY, int NZ, FluxCap<T> fc) {
+                                                 double* __restrict__ partial, int NY, int NZ, FluxCap<T> fc,
+                                                 const unsigned char* __restrict__ fmask) {
   const int p = blockIdx.y;
   const int i0 = planes[p];
   const bool pxp = g.per & 1;
@@ -1268,11 +1269,8 @@ __global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, Lag<T> L, 
   if (e < NY * NZ) {
     const int j = e / NZ, k = e - j * NZ;
     const T* cb = fc.buf ? fc.buf + (long long)p * 6 * fc.nn + e : nullptr;
-    // far tile at (i, j, k): the capture holds the value there
-    auto captured = [&](int i) {
-      return cb && i < g.nx && j < g.ny && k < g.nz && L.far[(i >> 6) + L.gx * ((j >> 2) + L.gy * (k / L.kc))];
-    };
-    const bool c0 = captured(i0), cm = captured(im);
+    const unsigned m = cb ? fmask[(long long)p * NY * NZ + e] : 0u;
+    const bool c0 = m & 1u, cm = m & 2u;
     if (j < g.ny) {
       const double hzm = cm ? D(cb[3 * fc.nn]) : h_level(g, F, L, 2, im, j, k);
       const double hz0 = c0 ? D(cb[5 * fc.nn]) : h_level(g, F, L, 2, i0, j, k);
@@ -1287,45 +1285,51 @@ __global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, Lag<T> L, 
     }
   }
   __shared__ double r1[256], r2[256];
-  __shared__ bool last;
-  auto tree = [&]() {
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) {
-        r1[threadIdx.x] += r1[threadIdx.x + w];
-        r2[threadIdx.x] += r2[threadIdx.x + w];
-      }
-      __syncthreads();
-    }
-  };
   r1[threadIdx.x] = s1;
   r2[threadIdx.x] = s2;
-  tree();
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      r1[threadIdx.x] += r1[threadIdx.x + w];
+      r2[threadIdx.x] += r2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     partial[(size_t)p * 2 * nb + 2 * blockIdx.x] = r1[0];
     partial[(size_t)p * 2 * nb + 2 * blockIdx.x + 1] = r2[0];
-    __threadfence();
-    const unsigned int tk = atomicAdd(&ticket[p], 1u);
-    last = (tk == (unsigned)nb - 1);
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // thread t sums the partials t, t + 256, ... in order, then the fixed tree
+}
+
+// The plane sums of probe_flux (block p: plane p): thread t adds the
+// partials t, t + 256, ... in order, then a fixed tree; P = dy dz (sum1 -
+// sum2) into the series and dt P into the time integral.
+__global__ __launch_bounds__(256) void probe_flux_sum(const double* __restrict__ partial, int nb,
+                                                      const int* __restrict__ slots, double* __restrict__ series,
+                                                      size_t cap, double* __restrict__ sums, long step, double dt,
+                                                      double dydz) {
+  const int p = blockIdx.x;
   const double* pp = partial + (size_t)p * 2 * nb;
   double a = 0.0, b = 0.0;
   for (int q = threadIdx.x; q < nb; q += blockDim.x) {
-    a += __hip_atomic_load(&pp[2 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    b += __hip_atomic_load(&pp[2 * q + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    a += pp[2 * q];
+    b += pp[2 * q + 1];
   }
+  __shared__ double r1[256], r2[256];
   r1[threadIdx.x] = a;
   r2[threadIdx.x] = b;
-  tree();
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      r1[threadIdx.x] += r1[threadIdx.x + w];
+      r2[threadIdx.x] += r2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     const double P = dydz * (r1[0] - r2[0]);
     series[(size_t)slots[p] * cap + step] = P;
     sums[slots[p]] += dt * P;
-    ticket[p] = 0u;
   }
 }
 

@@ -165,9 +165,9 @@ struct mm_ctx {
   int* d_slots;
   int nflux;
   double* d_partial;
-  unsigned int* d_ticket;
   int flux_blocks;
   void* d_fcap;           // flux-plane capture of the far tiles' fused pass, or null
+  unsigned char* d_fmask;  // per plane node: which of its entries the capture holds
   bool probes_frozen;
 
   long step;
@@ -191,6 +191,7 @@ struct mm_ctx {
   int *d_tl_all, *d_tl_near, *d_tl_far;
   int n_all, n_near, n_far;
   unsigned char* d_far;      // per tile id: 1 if far
+  std::vector<unsigned char> h_farv;   // the same, on the host
   long long cells_near, cells_far;
   int* d_tl_pml;             // tiles holding open-boundary layer entries
   int n_pml;
@@ -450,6 +451,33 @@ mm_status grow_buffers(mm_ctx* c, size_t need_steps) {
   return MM_OK;
 }
 
+// Which entries of each flux-plane node the capture holds: bit 0 for the
+// node's x = i0 entries, bit 1 for its x = im ones, set when that column of
+// the node is inside the grid and in a far tile.
+mm_status flux_mask(mm_ctx* c) {
+  if (!c->d_fmask) return MM_OK;
+  const int NY = nodes(c, 1), NZ = nodes(c, 2);
+  std::vector<unsigned char> mask((size_t)c->nflux * NY * NZ, 0);
+  int p = 0;
+  for (const ProbeRec& r : c->probes) {
+    if (r.d.kind == 0) continue;
+    const int i0 = r.d.i;
+    const int im = (c->per & 1) && i0 == 0 ? c->nx - 1 : i0 - 1;
+    for (int j = 0; j < NY; ++j)
+      for (int k = 0; k < NZ; ++k) {
+        auto far_at = [&](int i) {
+          if (i < 0 || i >= c->nx || j >= c->ny || k >= c->nz || c->h_farv.empty()) return false;
+          const size_t id = (size_t)(i / 64) + (size_t)c->tgx * ((size_t)(j / 4) + (size_t)c->tgy * (size_t)(k / c->tkc));
+          return c->h_farv[id] != 0;
+        };
+        mask[(size_t)p * NY * NZ + (size_t)j * NZ + k] = (far_at(i0) ? 1 : 0) | (far_at(im) ? 2 : 0);
+      }
+    ++p;
+  }
+  HIPCHECK(c, hipMemcpy(c->d_fmask, mask.data(), mask.size(), hipMemcpyHostToDevice));
+  return MM_OK;
+}
+
 mm_status freeze_probes(mm_ctx* c) {
   if (c->probes_frozen) return MM_OK;
   c->probes_frozen = true;
@@ -482,12 +510,10 @@ mm_status freeze_probes(mm_ctx* c) {
     c->d_planes = (int*)dalloc(c, planes.size() * sizeof(int));
     c->d_slots = (int*)dalloc(c, slots.size() * sizeof(int));
     c->d_partial = (double*)dalloc(c, (size_t)c->nflux * 2 * c->flux_blocks * sizeof(double));
-    c->d_ticket = (unsigned int*)dalloc(c, (size_t)c->nflux * sizeof(unsigned int));
-    if (!c->d_planes || !c->d_slots || !c->d_partial || !c->d_ticket)
+    if (!c->d_planes || !c->d_slots || !c->d_partial)
       return fail(c, MM_ENOMEM, "probe allocation failed");
     HIPCHECK(c, hipMemcpy(c->d_planes, planes.data(), planes.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(c->d_slots, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIPCHECK(c, hipMemset(c->d_ticket, 0, (size_t)c->nflux * sizeof(unsigned int)));
     // the far tiles' pass stores at most one plane per 64-column tile row
     // and role (x = i0, x = im)
     bool fcap = c->nflux <= mmk::kCapPlanes;
@@ -499,7 +525,10 @@ mm_status freeze_probes(mm_ctx* c) {
       }
     if (fcap) {
       c->d_fcap = dalloc(c, (size_t)c->nflux * 6 * nodes(c, 1) * nodes(c, 2) * c->esz);
-      if (!c->d_fcap) return fail(c, MM_ENOMEM, "probe allocation failed");
+      c->d_fmask = (unsigned char*)dalloc(c, (size_t)c->nflux * nodes(c, 1) * nodes(c, 2));
+      if (!c->d_fcap || !c->d_fmask) return fail(c, MM_ENOMEM, "probe allocation failed");
+      mm_status ms = flux_mask(c);
+      if (ms) return ms;
     }
   }
   return MM_OK;
@@ -990,8 +1019,10 @@ mm_status record_probes(mm_ctx* c, bool lagged = false, int which = 3, bool capt
   if ((which & 2) && c->nflux) {
     const int NY = nodes(c, 1), NZ = nodes(c, 2);
     hipLaunchKernelGGL((mmk::probe_flux<T>), dim3(c->flux_blocks, c->nflux), dim3(256), 0, c->stream, g, F, L,
-                       c->d_planes, c->d_slots, c->d_partial, c->d_ticket, c->d_series, c->series_cap,
-                       c->d_sums, c->step, c->dt, c->dy * c->dz, NY, NZ, flux_cap<T>(c, captured));
+                       c->d_planes, c->d_partial, NY, NZ, flux_cap<T>(c, captured), c->d_fmask);
+    hipLaunchKernelGGL(mmk::probe_flux_sum, dim3(c->nflux), dim3(256), 0, c->stream, c->d_partial,
+                       c->flux_blocks, c->d_slots, c->d_series, c->series_cap, c->d_sums, c->step, c->dt,
+                       c->dy * c->dz);
   }
   HIPCHECK(c, hipGetLastError());
   return MM_OK;
@@ -1351,6 +1382,7 @@ mm_status build_tiles(mm_ctx* c) {
   if (!nr.empty()) HIPCHECK(c, hipMemcpy(c->d_tl_near, nr.data(), nr.size() * sizeof(int), hipMemcpyHostToDevice));
   if (!fr.empty()) HIPCHECK(c, hipMemcpy(c->d_tl_far, fr.data(), fr.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPCHECK(c, hipMemcpy(c->d_far, far.data(), nt, hipMemcpyHostToDevice));
+  c->h_farv = far;
   return MM_OK;
 }
 
@@ -2095,6 +2127,7 @@ mm_status add_hard(mm_ctx* c, int field, const double* profile, double f0, doubl
     for (void* q : old)
       if (q) dfree(c, q);
     mm_status ts = build_tiles(c);
+    if (!ts) ts = flux_mask(c);
     if (ts) return ts;
   }
   return MM_OK;

@@ -468,12 +468,20 @@ __global__ __launch_bounds__(256) void h_half_db(Geo g, const T* __restrict__ Hx
                                                 T* __restrict__ Hyo, T* __restrict__ Hzo,
                                                 const T* __restrict__ Ex, const T* __restrict__ Ey,
                                                 const T* __restrict__ Ez, const T* __restrict__ mu, T coef0, T h,
-                                                Tiles tl) {
+                                                Tiles tl, FluxCap<T> cap = {}) {
   int i, j, k0, k1;
   tile_span(tl, g.nz, i, j, k0, k1);
+  const int tx = i;
   i += threadIdx.x;
   j += threadIdx.y;
-  if (i >= g.nx || j >= g.ny || k0 >= k1) return;
+  // flux-plane capture of the near tiles' plane nodes at level n+1 (the
+  // last half step of a step; see CapRole)
+  __shared__ T stash[4 * 6 * kCapPlanesZ];
+  const CapRole cr = cap_role(cap, tx, j, k0);
+  if (j >= g.ny || k0 >= k1) return;
+  const bool capw = cr.l0 >= 0 || cr.lm >= 0;   // wave-uniform
+  T* st = stash + __builtin_amdgcn_readfirstlane(threadIdx.y) * 6 * kCapPlanesZ;
+  if (i < g.nx) {
   const bool pxp = g.per & 1, pyp = g.per & 2, pzp = g.per & 4;
   const bool iin = pxp || i >= 1;
   const bool jin = pyp || j >= 1;
@@ -504,20 +512,26 @@ __global__ __launch_bounds__(256) void h_half_db(Geo g, const T* __restrict__ Hx
       const T cf = MU ? h / (mu0 * (half * (mu_im + mu_c))) : coef0;
       Hxo[c] = Hxi[c] - cf * curl;
     }
+    T hy1 = Hyi[c], hz1 = Hzi[c];
     if (jin) {
       const T curl = dq(ex_kp - ex_k, sdz, idz) - dq(ez_ip - ez, sdx, idx);
       const T cf = MU ? h / (mu0 * (half * (mu_jm + mu_c))) : coef0;
-      Hyo[c] = Hyi[c] - cf * curl;
+      hy1 = hy1 - cf * curl;
+      Hyo[c] = hy1;
     }
     if (pzp || k >= 1) {
       const T curl = dq(ey_ip - ey_k, sdx, idx) - dq(ex_jp - ex_k, sdy, idy);
       const T cf = MU ? h / (mu0 * (half * (mu_km + mu_c))) : coef0;
-      Hzo[c] = Hzi[c] - cf * curl;
+      hz1 = hz1 - cf * curl;
+      Hzo[c] = hz1;
     }
+    if (capw) cap_park(cr, st, k - k0, ey_k, ez, hy1, hz1);
     ex_k = ex_kp;
     ey_k = ey_kp;
     if (MU) mu_km = mu_c;
   }
+  }
+  if (capw) cap_flush(cr, cap, st, k1 - k0);
 }
 
 // Copy H (three components) on the cells of the listed tiles.

@@ -333,6 +333,74 @@ struct FluxCap {
   long long nn;            // plane nodes, NY * NZ
 };
 
+// Capture roles of one wave (one x row of 64 columns from tx, at one j): the
+// lane whose column is x = i0 of a plane and the lane whose column is its
+// x = im (or -1), with the offsets of node (j, k0) in that plane's capture;
+// all wave-uniform.  During a z-march the capture lanes park their values in
+// LDS (no global store inside a pipelined loop); afterwards the wave writes
+// them out, one lane per plane (runs of at most kCapPlanesZ planes).
+struct CapRole {
+  int l0, lm;
+  long long o0, om;
+};
+
+template <typename T>
+__device__ __forceinline__ CapRole cap_role(const FluxCap<T>& cap, int tx, int j, int k0) {
+  CapRole r{-1, -1, 0, 0};
+  if (!cap.buf) return r;
+  const long long jw = __builtin_amdgcn_readfirstlane(j);
+  for (int p = 0; p < cap.n; ++p) {
+    const long long b = (long long)p * 6 * cap.nn + jw * cap.NZ + k0;
+    if (cap.i0[p] >= tx && cap.i0[p] < tx + 64) {
+      r.l0 = cap.i0[p] - tx;
+      r.o0 = b;
+    }
+    if (cap.im[p] >= tx && cap.im[p] < tx + 64) {
+      r.lm = cap.im[p] - tx;
+      r.om = b + 2 * cap.nn;
+    }
+  }
+  return r;
+}
+
+// Park plane kk's values (E_y, E_z at i0; H_y, H_z at level n+1) in the
+// wave's stash st (6 x kCapPlanesZ).
+template <typename T>
+__device__ __forceinline__ void cap_park(const CapRole& r, T* st, int kk, T ey, T ez, T hy, T hz) {
+  if ((int)threadIdx.x == r.l0) {
+    st[kk] = ey;
+    st[kCapPlanesZ + kk] = ez;
+    st[4 * kCapPlanesZ + kk] = hy;
+    st[5 * kCapPlanesZ + kk] = hz;
+  }
+  if ((int)threadIdx.x == r.lm) {
+    st[2 * kCapPlanesZ + kk] = hy;
+    st[3 * kCapPlanesZ + kk] = hz;
+  }
+}
+
+// Write the n parked planes out (every lane of the wave takes part).
+template <typename T>
+__device__ __forceinline__ void cap_flush(const CapRole& r, const FluxCap<T>& cap, const T* st, int n) {
+  // the LDS writes came from other lanes of this wave
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int kk = threadIdx.x;   // node (j, k0 + kk): consecutive lanes, consecutive addresses
+  if (kk < n) {
+    if (r.l0 >= 0) {
+      cap.buf[r.o0 + kk] = st[kk];
+      cap.buf[r.o0 + cap.nn + kk] = st[kCapPlanesZ + kk];
+      cap.buf[r.o0 + 4 * cap.nn + kk] = st[4 * kCapPlanesZ + kk];
+      cap.buf[r.o0 + 5 * cap.nn + kk] = st[5 * kCapPlanesZ + kk];
+    }
+    if (r.lm >= 0) {
+      cap.buf[r.om + kk] = st[2 * kCapPlanesZ + kk];
+      cap.buf[r.om + cap.nn + kk] = st[3 * kCapPlanesZ + kk];
+    }
+  }
+}
+
 template <typename T, bool MU, int NP>
 __global__ __launch_bounds__(256) void h_bulk(Geo g, T* __restrict__ Hx, T* __restrict__ Hy,
                                              T* __restrict__ Hz, const T* __restrict__ Ex,
@@ -344,31 +412,12 @@ __global__ __launch_bounds__(256) void h_bulk(Geo g, T* __restrict__ Hx, T* __re
   const int tx = i;
   i += threadIdx.x;
   j += threadIdx.y;
-  // flux-plane capture roles of this wave (one x row of 64 at one j): the
-  // lane whose column is x = i0 of a plane and the lane whose column is its
-  // x = im, with the offsets of node (j, k0) in that plane's capture; all
-  // wave-uniform.  During the march the capture lanes park their values in
-  // LDS (no global store inside the pipelined loop); afterwards the wave
-  // writes them out, one lane per plane (tiles of at most kCapPlanesZ planes).
+  // flux-plane capture (see CapRole)
   __shared__ T stash[NP == 2 ? 4 * 6 * kCapPlanesZ : 1];
-  int l0 = -1, lm = -1;
-  long long o0 = 0, om = 0;
-  if (NP == 2 && cap.buf) {
-    const long long jw = __builtin_amdgcn_readfirstlane(j);
-    for (int p = 0; p < cap.n; ++p) {
-      const long long b = (long long)p * 6 * cap.nn + jw * cap.NZ + k0;
-      if (cap.i0[p] >= tx && cap.i0[p] < tx + 64) {
-        l0 = cap.i0[p] - tx;
-        o0 = b;
-      }
-      if (cap.im[p] >= tx && cap.im[p] < tx + 64) {
-        lm = cap.im[p] - tx;
-        om = b + 2 * cap.nn;
-      }
-    }
-  }
+  CapRole cr{-1, -1, 0, 0};
+  if (NP == 2) cr = cap_role(cap, tx, j, k0);
   if (j >= g.ny || k0 >= k1) return;
-  const bool capw = NP == 2 && (l0 >= 0 || lm >= 0);   // wave-uniform
+  const bool capw = NP == 2 && (cr.l0 >= 0 || cr.lm >= 0);   // wave-uniform
   T* st = stash + (NP == 2 ? __builtin_amdgcn_readfirstlane(threadIdx.y) * 6 * kCapPlanesZ : 0);
   if (i < g.nx) {
   const bool pxp = g.per & 1, pyp = g.per & 2, pzp = g.per & 4;
@@ -440,43 +489,13 @@ __global__ __launch_bounds__(256) void h_bulk(Geo g, T* __restrict__ Hx, T* __re
       for (int p = 1; p < NP; ++p) v = v - cf * curl;
       Hz[c] = v;
     }
-    if (capw) {   // capture: E and H at level n+1
-      const int kk = k - k0;
-      if ((int)threadIdx.x == l0) {
-        st[kk] = ey_k;
-        st[kCapPlanesZ + kk] = cur.ez;
-        st[4 * kCapPlanesZ + kk] = hy1;
-        st[5 * kCapPlanesZ + kk] = hz1;
-      }
-      if ((int)threadIdx.x == lm) {
-        st[2 * kCapPlanesZ + kk] = hy1;
-        st[3 * kCapPlanesZ + kk] = hz1;
-      }
-    }
+    if (capw) cap_park(cr, st, k - k0, ey_k, cur.ez, hy1, hz1);   // E and H at level n+1
     ex_k = cur.ex_kp;
     ey_k = cur.ey_kp;
     if (MU) mu_km = cur.mu_c;
   }
   }
-  if (capw) {
-    // the LDS writes above came from other lanes of this wave
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int kk = threadIdx.x;   // node (j, k0 + kk); consecutive lanes, consecutive addresses
-    if (kk < k1 - k0) {
-      if (l0 >= 0) {
-        cap.buf[o0 + kk] = st[kk];
-        cap.buf[o0 + cap.nn + kk] = st[kCapPlanesZ + kk];
-        cap.buf[o0 + 4 * cap.nn + kk] = st[4 * kCapPlanesZ + kk];
-        cap.buf[o0 + 5 * cap.nn + kk] = st[5 * kCapPlanesZ + kk];
-      }
-      if (lm >= 0) {
-        cap.buf[om + kk] = st[2 * kCapPlanesZ + kk];
-        cap.buf[om + cap.nn + kk] = st[3 * kCapPlanesZ + kk];
-      }
-    }
-  }
+  if (capw) cap_flush(cr, cap, st, k1 - k0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1252,13 +1271,15 @@ __global__ void probe_points(Geo g, Fields<T> F, Lag<T> L, const PointProbe* __r
 // With a capture (FluxCap.buf set; the far tiles' fused pass has run and
 // holds H^{n+3/2}), values at faces and edges of far tiles come from the
 // capture that pass stored on its way through level n+1; the near tiles'
-// values are read from the fields as without one.  fmask (per plane node,
-// bit 0: the node's x = i0 entries lie in a far tile, bit 1: its x = im
-// entries) says which; it is fixed by the tile split.
+// values are read from the fields as without one, or, with near != 0 (the
+// fused sub-step's last half step filled the capture as well), from the
+// capture where it holds them.  fmask says which entries of a node the
+// capture holds (bits 0-1 far tiles, 2-6 near tiles; fixed by the tile
+// split and the magnetic faces).
 template <typename T>
 __global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, Lag<T> L, const int* __restrict__ planes,
                                                  double* __restrict__ partial, int NY, int NZ, FluxCap<T> fc,
-                                                 const unsigned char* __restrict__ fmask) {
+                                                 const unsigned char* __restrict__ fmask, int near) {
   const int p = blockIdx.y;
   const int i0 = planes[p];
   const bool pxp = g.per & 1;
@@ -1269,19 +1290,23 @@ __global__ __launch_bounds__(256) void probe_flux(Geo g, Fields<T> F, Lag<T> L, 
   if (e < NY * NZ) {
     const int j = e / NZ, k = e - j * NZ;
     const T* cb = fc.buf ? fc.buf + (long long)p * 6 * fc.nn + e : nullptr;
-    const unsigned m = cb ? fmask[(long long)p * NY * NZ + e] : 0u;
-    const bool c0 = m & 1u, cm = m & 2u;
+    unsigned m = cb ? fmask[(long long)p * NY * NZ + e] : 0u;
+    // per entry: far tile (bit 0 / 1) or, when the near tiles filled it, near
+    m = (m & 3u) | (near ? (m & 124u) : 0u);
+    const bool e0 = m & 5u;                              // E_y, E_z at i0
+    const bool hy0c = m & 9u, hz0c = m & 17u;            // H at i0
+    const bool hymc = m & 34u, hzmc = m & 66u;           // H at im
     if (j < g.ny) {
-      const double hzm = cm ? D(cb[3 * fc.nn]) : h_level(g, F, L, 2, im, j, k);
-      const double hz0 = c0 ? D(cb[5 * fc.nn]) : h_level(g, F, L, 2, i0, j, k);
+      const double hzm = hzmc ? D(cb[3 * fc.nn]) : h_level(g, F, L, 2, im, j, k);
+      const double hz0 = hz0c ? D(cb[5 * fc.nn]) : h_level(g, F, L, 2, i0, j, k);
       const double hz = 0.5 * (hzm + hz0);
-      s1 = (c0 ? D(cb[0]) : D(F.E[1][at(g, i0, j, k)])) * hz;
+      s1 = (e0 ? D(cb[0]) : D(F.E[1][at(g, i0, j, k)])) * hz;
     }
     if (k < g.nz) {
-      const double hym = cm ? D(cb[2 * fc.nn]) : h_level(g, F, L, 1, im, j, k);
-      const double hy0 = c0 ? D(cb[4 * fc.nn]) : h_level(g, F, L, 1, i0, j, k);
+      const double hym = hymc ? D(cb[2 * fc.nn]) : h_level(g, F, L, 1, im, j, k);
+      const double hy0 = hy0c ? D(cb[4 * fc.nn]) : h_level(g, F, L, 1, i0, j, k);
       const double hy = 0.5 * (hym + hy0);
-      s2 = (c0 ? D(cb[fc.nn]) : D(F.E[2][at(g, i0, j, k)])) * hy;
+      s2 = (e0 ? D(cb[fc.nn]) : D(F.E[2][at(g, i0, j, k)])) * hy;
     }
   }
   __shared__ double r1[256], r2[256];

@@ -168,6 +168,7 @@ struct mm_ctx {
   int flux_blocks;
   void* d_fcap;           // flux-plane capture of the far tiles' fused pass, or null
   unsigned char* d_fmask;  // per plane node: which of its entries the capture holds
+  bool fcap_near;          // this step's last near-tile half step fills the capture too
   bool probes_frozen;
 
   long step;
@@ -451,12 +452,24 @@ mm_status grow_buffers(mm_ctx* c, size_t need_steps) {
   return MM_OK;
 }
 
-// Which entries of each flux-plane node the capture holds: bit 0 for the
-// node's x = i0 entries, bit 1 for its x = im ones, set when that column of
-// the node is inside the grid and in a far tile.
+// Which entries of each flux-plane node the capture holds.  Far tiles (the
+// fused pass of the far tiles writes them): bit 0 for the node's x = i0
+// entries, bit 1 for its x = im entries.  Near tiles (the fused sub-step's
+// last half step writes them): bit 2 for E_y, E_z at i0, bits 3 and 4 for
+// H_y, H_z at i0, bits 5 and 6 for H_y, H_z at im, each unless that face
+// is an evolving magnetic face (its H comes from the iteration).  Only
+// entries inside the grid (i < nx, j < ny, k < nz).
 mm_status flux_mask(mm_ctx* c) {
   if (!c->d_fmask) return MM_OK;
   const int NY = nodes(c, 1), NZ = nodes(c, 2);
+  // evolving faces per family, sorted by padded index
+  std::vector<int> ev[3];
+  for (int t = 0; t < c->nmag; ++t) ev[c->h_fam[t]].push_back((int)c->h_idx[t]);
+  for (auto& v : ev) std::sort(v.begin(), v.end());
+  auto evolving = [&](int f, int i, int j, int k) {
+    const int pi = (int)pidx(c, i, j, k);
+    return std::binary_search(ev[f].begin(), ev[f].end(), pi);
+  };
   std::vector<unsigned char> mask((size_t)c->nflux * NY * NZ, 0);
   int p = 0;
   for (const ProbeRec& r : c->probes) {
@@ -465,12 +478,25 @@ mm_status flux_mask(mm_ctx* c) {
     const int im = (c->per & 1) && i0 == 0 ? c->nx - 1 : i0 - 1;
     for (int j = 0; j < NY; ++j)
       for (int k = 0; k < NZ; ++k) {
-        auto far_at = [&](int i) {
-          if (i < 0 || i >= c->nx || j >= c->ny || k >= c->nz || c->h_farv.empty()) return false;
+        auto tile_of = [&](int i) -> int {   // 1 far, 0 near, -1 outside the grid
+          if (i < 0 || i >= c->nx || j >= c->ny || k >= c->nz || c->h_farv.empty()) return -1;
           const size_t id = (size_t)(i / 64) + (size_t)c->tgx * ((size_t)(j / 4) + (size_t)c->tgy * (size_t)(k / c->tkc));
-          return c->h_farv[id] != 0;
+          return c->h_farv[id] != 0 ? 1 : 0;
         };
-        mask[(size_t)p * NY * NZ + (size_t)j * NZ + k] = (far_at(i0) ? 1 : 0) | (far_at(im) ? 2 : 0);
+        const int t0 = tile_of(i0), tm = tile_of(im);
+        unsigned char m = 0;
+        if (t0 == 1) m |= 1;
+        if (tm == 1) m |= 2;
+        if (t0 == 0) {
+          m |= 4;
+          if (!evolving(1, i0, j, k)) m |= 8;
+          if (!evolving(2, i0, j, k)) m |= 16;
+        }
+        if (tm == 0) {
+          if (!evolving(1, im, j, k)) m |= 32;
+          if (!evolving(2, im, j, k)) m |= 64;
+        }
+        mask[(size_t)p * NY * NZ + (size_t)j * NZ + k] = m;
       }
     ++p;
   }
@@ -698,6 +724,9 @@ mm_status apply_hard(mm_ctx* c, bool e_field, double t) {
 // d_Mb (Step 1); the far tiles stay in H.  run_steps copies the near tiles
 // H -> A when a run starts and A -> H when it ends.
 template <typename T>
+mmk::FluxCap<T> flux_cap(const mm_ctx* c, bool on);
+
+template <typename T>
 mm_status substep_fused(mm_ctx* c, bool near_only, bool step3) {
   const Geo g = make_geo(c);
   const double h = 0.5 * c->dt;
@@ -715,11 +744,12 @@ mm_status substep_fused(mm_ctx* c, bool near_only, bool step3) {
   if (c->n_near > 0) {
     const int split = split_for(c, c->n_near);
     const mmk::Tiles tl = tiles(c, c->d_tl_near, split);
+    const mmk::FluxCap<T> fc = flux_cap<T>(c, step3 && c->fcap_near);
     Timed tm(c, 1);
 #define MM_HDB(MU)                                                                                           \
   hipLaunchKernelGGL((mmk::h_half_db<T, MU>), dim3(c->n_near * split), dim3(64, 4), 0, c->stream, g, Hin[0], \
                      Hin[1], Hin[2], Hout[0], Hout[1], Hout[2], (const T*)c->E[0], (const T*)c->E[1],        \
-                     (const T*)c->E[2], (const T*)c->mu, (T)hmu0, (T)h, tl)
+                     (const T*)c->E[2], (const T*)c->mu, (T)hmu0, (T)h, tl, fc)
     if (c->mu) MM_HDB(true);
     else MM_HDB(false);
 #undef MM_HDB
@@ -1019,7 +1049,8 @@ mm_status record_probes(mm_ctx* c, bool lagged = false, int which = 3, bool capt
   if ((which & 2) && c->nflux) {
     const int NY = nodes(c, 1), NZ = nodes(c, 2);
     hipLaunchKernelGGL((mmk::probe_flux<T>), dim3(c->flux_blocks, c->nflux), dim3(256), 0, c->stream, g, F, L,
-                       c->d_planes, c->d_partial, NY, NZ, flux_cap<T>(c, captured), c->d_fmask);
+                       c->d_planes, c->d_partial, NY, NZ, flux_cap<T>(c, captured), c->d_fmask,
+                       (int)(captured && c->fcap_near));
     hipLaunchKernelGGL(mmk::probe_flux_sum, dim3(c->nflux), dim3(256), 0, c->stream, c->d_partial,
                        c->flux_blocks, c->d_slots, c->d_series, c->series_cap, c->d_sums, c->step, c->dt,
                        c->dy * c->dz);
@@ -1091,7 +1122,12 @@ mm_status run_steps(mm_ctx* c, int64_t n) {
     }
     if ((s = substep<T>(c, lagging))) return s;     // Step 1
     if ((s = e_step<T>(c))) return s;               // Step 2
-    if ((s = substep<T>(c, !end, true))) return s;  // Step 3
+    // the flux probe of a lagging step reads the near tiles' plane nodes from
+    // the capture as well when the fused sub-step's last half step fills it
+    c->fcap_near = !end && c->nflux && c->chain_fused && flux_captured(c);
+    s = substep<T>(c, !end, true);                  // Step 3
+    c->fcap_near = c->fcap_near && !s;
+    if (s) return s;
     if (end && c->chain_fused) {
       if ((s = copy_near<T>(c, false))) return s;
       c->chain_fused = false;
@@ -1100,6 +1136,7 @@ mm_status run_steps(mm_ctx* c, int64_t n) {
     if ((s = record_probes<T>(c, !end, cap ? 1 : 3))) return s;
     if (!end && (s = h_far<T>(c, cap))) return s;
     if (cap && (s = record_probes<T>(c, true, 2, true))) return s;
+    c->fcap_near = false;
     lagging = !end;
     c->step++;
   }

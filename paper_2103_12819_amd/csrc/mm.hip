@@ -664,10 +664,10 @@ mmk::Pml<T> make_pml(const mm_ctx* c) {
 }
 
 // z-split for a launch over n tiles: enough blocks to fill the chip
-// (~2048), runs of at least 4 planes.
+// (~4096 blocks, 16 waves per CU), runs of at least 4 planes.
 int split_for(const mm_ctx* c, int n) {
   if (n <= 0) return 1;
-  const int want = (2048 + n - 1) / n;
+  const int want = (4096 + n - 1) / n;
   return std::max(1, std::min(want, c->tkc / 4));
 }
 

@@ -122,7 +122,7 @@ struct mm_ctx {
   int* ctl_kpred;             // fused form: previous sub-step's iteration count
   unsigned long long* ctl_fpart;  // fused form: partials of hm_fused (2 parities x 4 rows x chunks)
 
-  // fused H-M sub-step (hm_fused.h): chunks of 60 x 4 columns x fL planes
+  // fused H-M sub-step (hm_fused.h): chunks of 30 x 6 columns x fL planes
   // holding evolving faces, their slot tables, the second M buffer (Step 1
   // writes it, Step 3 writes d_M back) and the device-side count
   int fuse_mode;              // mm_options.fused

@@ -5,7 +5,13 @@
 //   Step 1: H-M sub-step with curl E^n     (hm_pre -> h_bulk -> hm_step.. -> hm_finish -> hm_commit)
 //   Step 2: E update with the soft source   (e_update)
 //   Step 3: H-M sub-step with curl E^{n+1} (the same sequence)
-//   probes at level n+1                     (probe_points, probe_flux)
+//   probes at level n+1                     (probe_points, probe_flux, probe_flux_sum)
+// This file holds that per-iteration form of the H-M sub-step; grids with
+// many magnetic faces take the fused form of hm_fused.h (h_half_db ->
+// hm_fused -> hm_more, the same results).  Inside one mm_step call the
+// tiles away from magnetic faces take Step 3 of one step and Step 1 of the
+// next in one pass (h_bulk with NP = 2), which also fills the flux planes'
+// capture the probe reads.
 //
 // Storage: every field array (and every cell map) lives in one padded
 // layout, element (i,j,k) at i + px*j + sz*k with px >= nx+1 a multiple of

@@ -12,10 +12,11 @@
 //                         read by a magnetic face gathers 1/4 of its
 //                         readers' Q (fixed order, no atomics)
 //   * adj_mag_inv         reverse of b, d, q (eq:llg_tra5/6, eq:iterate_H)
-//   * adj_face_pass       reverse of the non-magnetic Faraday update: the
-//                         face cotangent T splits into the H^s cotangent and
+//   * adj_touch,          reverse of the non-magnetic Faraday update: the
+//     adj_zero_walls      face cotangent T splits into the H^s cotangent and
 //                         C = -(dt/2 mu0) T for curl E
-//   * add_curl_h          E_bar += curl H(C) (transpose of curl E)
+//   * add_curl_h          E_bar += curl H(C) (transpose of curl E), C read
+//                         from the face cotangents as they stand
 //   * adj_e_coef          reverse of Step 2 per edge: E_bar <- ca E_bar,
 //                         W = cb E_bar, d L / d eps_e accumulated
 //   * h_bulk(coef = -1)   H_bar += curl E(W) (transpose of curl H)
@@ -302,40 +303,59 @@ __global__ __launch_bounds__(256) void adj_mag_inv(AdjMag a, T* Xb0, T* Xb1, T* 
   for (int q = 0; q < 3; ++q) a.Mb[q][t] = mb[q];
 }
 
-// Per face: T = Hb + Xb is the cotangent of the face's Faraday value; the
-// H^s cotangent becomes T + Gb and C_bar = -(dt/2 mu0) T feeds curl E.
-// Wall faces (constant) get 0.
+// The reverse of the non-magnetic Faraday update, per face: T = Hb + Xb is
+// the cotangent of the face's Faraday value; the H^s cotangent becomes
+// T + Gb and C = -(dt/2 mu0) T feeds curl E.  Wall faces (constant) get 0.
+// Xb and Gb are zero off the touched faces, so the pass runs in three
+// parts: adj_touch (mode 0) adds Xb on the touched faces, add_curl_h reads
+// C straight from Hb, adj_touch (mode 1) adds Gb and clears Xb and Gb, and
+// adj_zero_walls clears the wall faces.  A face counts when it lies in the
+// grid (0 <= i < nx, ...) and is interior along its own axis.
 template <typename T>
-__global__ __launch_bounds__(256) void adj_face_pass(Geo g, T* Hb0, T* Hb1, T* Hb2, const T* Xb0,
-                                                    const T* Xb1, const T* Xb2, const T* Gb0, const T* Gb1,
-                                                    const T* Gb2, T* W0, T* W1, T* W2, double hmu0) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * 4 + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny || k >= g.nz) return;
-  const int c = at(g, i, j, k);
-  const bool in[3] = {(g.per & 1) || i >= 1, (g.per & 2) || j >= 1, (g.per & 4) || k >= 1};
-  T* Hb[3] = {Hb0, Hb1, Hb2};
-  const T* Xb[3] = {Xb0, Xb1, Xb2};
-  const T* Gb[3] = {Gb0, Gb1, Gb2};
-  T* W[3] = {W0, W1, W2};
-  for (int f = 0; f < 3; ++f) {
-    if (in[f]) {
-      const double tt = D(Hb[f][c]) + D(Xb[f][c]);
-      Hb[f][c] = (T)(tt + D(Gb[f][c]));
-      W[f][c] = (T)(-hmu0 * tt);
-    } else {
-      Hb[f][c] = (T)0;
-      W[f][c] = (T)0;
-    }
+__global__ __launch_bounds__(256) void adj_touch(Geo g, const int* __restrict__ tidx,
+                                                const unsigned char* __restrict__ tfam, int nt, T* Hb0, T* Hb1,
+                                                T* Hb2, T* Xb0, T* Xb1, T* Xb2, T* Gb0, T* Gb1, T* Gb2, int mode) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= nt) return;
+  const int f = tfam[u], c = tidx[u];
+  T* X = f == 0 ? Xb0 : (f == 1 ? Xb1 : Xb2);
+  T* G = f == 0 ? Gb0 : (f == 1 ? Gb1 : Gb2);
+  T* H = f == 0 ? Hb0 : (f == 1 ? Hb1 : Hb2);
+  int p[3];
+  face_ijk(g, c, p[0], p[1], p[2]);
+  const bool inside = p[0] < g.nx && p[1] < g.ny && p[2] < g.nz && (((g.per >> f) & 1) || p[f] >= 1);
+  if (mode == 0) {
+    if (inside) H[c] = (T)(D(H[c]) + D(X[c]));
+  } else {
+    if (inside) H[c] = (T)(D(H[c]) + D(G[c]));
+    X[c] = (T)0;
+    G[c] = (T)0;
   }
 }
 
-// E_bar += curl H(W) on interior edges (W a face field).
+// Wall faces: Hb of family f is cleared on the plane (axis f) = 0 unless the
+// axis is periodic.  blockIdx.y = f; x runs over the plane's faces.
+template <typename T>
+__global__ __launch_bounds__(256) void adj_zero_walls(Geo g, T* Hb0, T* Hb1, T* Hb2) {
+  const int f = blockIdx.y;
+  if ((g.per >> f) & 1) return;
+  const int a = f == 0 ? g.ny : g.nx;   // the plane's first axis (y for f = 0, else x)
+  const int b = f == 2 ? g.ny : g.nz;   // its second (z for f = 0 and 1, y for f = 2)
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)a * b) return;
+  const int u = (int)(e % a), v = (int)(e / a);
+  if (f == 0) Hb0[at(g, 0, u, v)] = (T)0;
+  else if (f == 1) Hb1[at(g, u, 0, v)] = (T)0;
+  else Hb2[at(g, u, v, 0)] = (T)0;
+}
+
+// E_bar += curl H(C) on interior edges, C = scale * W (W a face field).  Every
+// face value an update uses is interior along its own axis.
 template <typename T>
 __global__ __launch_bounds__(256) void add_curl_h(Geo g, T* __restrict__ Eb0, T* __restrict__ Eb1,
                                                  T* __restrict__ Eb2, const T* __restrict__ W0,
-                                                 const T* __restrict__ W1, const T* __restrict__ W2, int kchunk) {
+                                                 const T* __restrict__ W1, const T* __restrict__ W2, double scale,
+                                                 int kchunk) {
   const int i = blockIdx.x * 64 + threadIdx.x;
   const int j = blockIdx.y * 4 + threadIdx.y;
   if (i >= g.nx || j >= g.ny) return;
@@ -350,15 +370,15 @@ __global__ __launch_bounds__(256) void add_curl_h(Geo g, T* __restrict__ Eb0, T*
   T wx_km = 0, wy_km = 0;
   if (pzp || k0 >= 1) {
     const int km = dn(k0, g.nz, pzp);
-    wx_km = W0[at(g, i, j, km)];
-    wy_km = W1[at(g, i, j, km)];
+    wx_km = (T)(scale * D(W0[at(g, i, j, km)]));
+    wy_km = (T)(scale * D(W1[at(g, i, j, km)]));
   }
   for (int k = k0; k < k1; ++k) {
     const bool kin = pzp || k >= 1;
     const int c = at(g, i, j, k);
-    const T wx = W0[c], wy = W1[c], wz = W2[c];
-    const T wz_jm = W2[at(g, i, jm, k)], wx_jm = W0[at(g, i, jm, k)];
-    const T wz_im = W2[at(g, im, j, k)], wy_im = W1[at(g, im, j, k)];
+    const T wx = (T)(scale * D(W0[c])), wy = (T)(scale * D(W1[c])), wz = (T)(scale * D(W2[c]));
+    const T wz_jm = (T)(scale * D(W2[at(g, i, jm, k)])), wx_jm = (T)(scale * D(W0[at(g, i, jm, k)]));
+    const T wz_im = (T)(scale * D(W2[at(g, im, j, k)])), wy_im = (T)(scale * D(W1[at(g, im, j, k)]));
     if (jin && kin) Eb0[c] = Eb0[c] + (dq(wz - wz_jm, sdy, idy) - dq(wy - wy_km, sdz, idz));
     if (iin && kin) Eb1[c] = Eb1[c] + (dq(wx - wx_km, sdz, idz) - dq(wz - wz_im, sdx, idx));
     if (iin && jin) Eb2[c] = Eb2[c] + (dq(wy - wy_im, sdx, idx) - dq(wx - wx_jm, sdy, idy));
@@ -384,17 +404,6 @@ __global__ __launch_bounds__(256) void copy_batch(CopyBatch b) {
   for (unsigned long long q = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
        q += (unsigned long long)gridDim.x * blockDim.x)
     d[q] = s[q];
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void zero_touched(const int* __restrict__ tidx,
-                                                   const unsigned char* __restrict__ tfam, int nt, T* Xb0,
-                                                   T* Xb1, T* Xb2, T* Gb0, T* Gb1, T* Gb2) {
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= nt) return;
-  const int f = tfam[u], c = tidx[u];
-  (f == 0 ? Xb0 : (f == 1 ? Xb1 : Xb2))[c] = (T)0;
-  (f == 0 ? Gb0 : (f == 1 ? Gb1 : Gb2))[c] = (T)0;
 }
 
 // Reverse of Step 2 on every interior edge: with D = eps/dt + sigma/2,

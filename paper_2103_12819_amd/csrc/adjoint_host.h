@@ -345,16 +345,22 @@ mm_status adj_substep(mm_ctx* c, T* const* Hs, const double* Ms0, T* const* Ho, 
                        w.dQ, a, Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], 1);
     HIPCHECK(c, hipGetLastError());
   }
-  const dim3 fgrid((c->nx + 63) / 64, (c->ny + 3) / 4, c->nz);
-  hipLaunchKernelGGL((mmk::adj_face_pass<T>), fgrid, dim3(64, 4), 0, c->stream, g, Hb[0], Hb[1], Hb[2], Xb[0],
-                     Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], Wv[0], Wv[1], Wv[2], 0.5 * c->dt / mmk::kMu0);
+  // the face pass: T = Hb + Xb on the touched faces, C = -(dt/2 mu0) T into
+  // curl E's transpose, then Hb = T + Gb and the wall faces cleared
+  const int tb = (w.nt + 255) / 256;
+  if (w.nt > 0)
+    hipLaunchKernelGGL((mmk::adj_touch<T>), dim3(tb), dim3(256), 0, c->stream, g, w.tidx, w.tfam, w.nt, Hb[0],
+                       Hb[1], Hb[2], Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], 0);
   dim3 grid;
   const int kc = kchunk_for(c, grid);
-  hipLaunchKernelGGL((mmk::add_curl_h<T>), grid, dim3(64, 4), 0, c->stream, g, Eb[0], Eb[1], Eb[2], Wv[0], Wv[1],
-                     Wv[2], kc);
-  if (c->nmag > 0)
-    hipLaunchKernelGGL((mmk::zero_touched<T>), dim3((w.nt + 255) / 256), dim3(256), 0, c->stream, w.tidx, w.tfam,
-                       w.nt, Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2]);
+  hipLaunchKernelGGL((mmk::add_curl_h<T>), grid, dim3(64, 4), 0, c->stream, g, Eb[0], Eb[1], Eb[2],
+                     (const T*)Hb[0], (const T*)Hb[1], (const T*)Hb[2], -0.5 * c->dt / mmk::kMu0, kc);
+  if (w.nt > 0)
+    hipLaunchKernelGGL((mmk::adj_touch<T>), dim3(tb), dim3(256), 0, c->stream, g, w.tidx, w.tfam, w.nt, Hb[0],
+                       Hb[1], Hb[2], Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], 1);
+  const long long wall = std::max({(long long)c->ny * c->nz, (long long)c->nx * c->nz, (long long)c->nx * c->ny});
+  hipLaunchKernelGGL((mmk::adj_zero_walls<T>), dim3((unsigned)((wall + 255) / 256), 3), dim3(256), 0, c->stream, g,
+                     Hb[0], Hb[1], Hb[2]);
   HIPCHECK(c, hipGetLastError());
   return MM_OK;
 }

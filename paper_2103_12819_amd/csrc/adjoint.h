@@ -409,7 +409,9 @@ __global__ __launch_bounds__(256) void copy_batch(CopyBatch b) {
 // Reverse of Step 2 on every interior edge: with D = eps/dt + sigma/2,
 // ca = (eps/dt - sigma/2)/D, cb = 1/D:  d ca/d eps = (sigma/dt)/D^2,
 // d cb/d eps = -(1/dt)/D^2.  epsb accumulates E_bar (E^n d ca + (curl H - J g) d cb);
-// W = cb E_bar (to H through curl E), E_bar <- ca E_bar.
+// W = cb E_bar (to H through curl E), E_bar <- ca E_bar.  First, the curl
+// transpose of the Step 3 reverse that precedes it: E_bar += curl H(C) with
+// C = cscale * Cf (the same per-edge expression as add_curl_h).
 template <typename T, bool SIG>
 __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T* __restrict__ Eb1,
                                                  T* __restrict__ Eb2, const T* __restrict__ En0,
@@ -419,7 +421,8 @@ __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T*
                                                  const T* __restrict__ sig, T* __restrict__ W0, T* __restrict__ W1,
                                                  T* __restrict__ W2, double* __restrict__ epsb0,
                                                  double* __restrict__ epsb1, double* __restrict__ epsb2, T dt,
-                                                 Src src, int kchunk) {
+                                                 Src src, const T* __restrict__ Cf0, const T* __restrict__ Cf1,
+                                                 const T* __restrict__ Cf2, double cscale, int kchunk) {
   const int i = blockIdx.x * 64 + threadIdx.x;
   const int j = blockIdx.y * 4 + threadIdx.y;
   if (i >= g.nx || j >= g.ny) return;
@@ -433,10 +436,13 @@ __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T*
   const T sdx = (T)g.dx, sdy = (T)g.dy, sdz = (T)g.dz;
   const T e0 = (T)kEps0, half = (T)0.5, quarter = (T)0.25;
   T hx_km = 0, hy_km = 0, e_km = 0, e_jm_km = 0, e_im_km = 0, s_km = 0, s_jm_km = 0, s_im_km = 0;
+  T wx_km = 0, wy_km = 0;
   if (pzp || k0 >= 1) {
     const int km = dn(k0, g.nz, pzp);
     hx_km = Hx[at(g, i, j, km)];
     hy_km = Hy[at(g, i, j, km)];
+    wx_km = (T)(cscale * D(Cf0[at(g, i, j, km)]));
+    wy_km = (T)(cscale * D(Cf1[at(g, i, j, km)]));
     e_km = eps[at(g, i, j, km)];
     e_jm_km = eps[at(g, i, jm, km)];
     e_im_km = eps[at(g, im, j, km)];
@@ -452,6 +458,9 @@ __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T*
     const int cjm = at(g, i, jm, k), cim = at(g, im, j, k);
     const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
     const T hz_jm = Hz[cjm], hx_jm = Hx[cjm], hz_im = Hz[cim], hy_im = Hy[cim];
+    const T wx = (T)(cscale * D(Cf0[c])), wy = (T)(cscale * D(Cf1[c])), wz = (T)(cscale * D(Cf2[c]));
+    const T wz_jm = (T)(cscale * D(Cf2[cjm])), wx_jm = (T)(cscale * D(Cf0[cjm]));
+    const T wz_im = (T)(cscale * D(Cf2[cim])), wy_im = (T)(cscale * D(Cf1[cim]));
     const T e_c = eps[c], e_jm = eps[cjm], e_im = eps[cim], e_imjm = eps[at(g, im, jm, k)];
     T s_c = 0, s_jm = 0, s_im = 0, s_imjm = 0;
     if (SIG) {
@@ -485,6 +494,7 @@ __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T*
       T curl = dq(hz - hz_jm, sdy, idy) - dq(hy - hy_km, sdz, idz);
       if (src.comp == 0) curl = curl - (T)src_term(src, 0, i, j, k);
       T eb = Eb0[c], w;
+      if (jin && kin) eb = eb + (dq(wz - wz_jm, sdy, idy) - dq(wy - wy_km, sdz, idz));
       double eps_acc = epsb0[c];
       edge(jin && kin, (e_jm_km + e_km) + (e_jm + e_c), (s_jm_km + s_km) + (s_jm + s_c), curl, En0[c], eb, w,
            eps_acc);
@@ -496,6 +506,7 @@ __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T*
       T curl = dq(hx - hx_km, sdz, idz) - dq(hz - hz_im, sdx, idx);
       if (src.comp == 1) curl = curl - (T)src_term(src, 1, i, j, k);
       T eb = Eb1[c], w;
+      if (iin && kin) eb = eb + (dq(wx - wx_km, sdz, idz) - dq(wz - wz_im, sdx, idx));
       double eps_acc = epsb1[c];
       edge(iin && kin, (e_im_km + e_km) + (e_im + e_c), (s_im_km + s_km) + (s_im + s_c), curl, En1[c], eb, w,
            eps_acc);
@@ -507,6 +518,7 @@ __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T*
       T curl = dq(hy - hy_im, sdx, idx) - dq(hx - hx_jm, sdy, idy);
       if (src.comp == 2) curl = curl - (T)src_term(src, 2, i, j, k);
       T eb = Eb2[c], w;
+      if (iin && jin) eb = eb + (dq(wy - wy_im, sdx, idx) - dq(wx - wx_jm, sdy, idy));
       double eps_acc = epsb2[c];
       edge(iin && jin, (e_imjm + e_jm) + (e_im + e_c), (s_imjm + s_jm) + (s_im + s_c), curl, En2[c], eb, w,
            eps_acc);
@@ -516,6 +528,8 @@ __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T*
     }
     hx_km = hx;
     hy_km = hy;
+    wx_km = wx;
+    wy_km = wy;
     e_km = e_c;
     e_jm_km = e_jm;
     e_im_km = e_im;

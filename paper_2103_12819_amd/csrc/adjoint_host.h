@@ -124,43 +124,56 @@ void addM(const mm_ctx* c, CopyList& L, double* blk, bool save) {
 }
 
 // Faces that evolving magnetic faces read (themselves and their 8
-// transverse neighbours), each once, with its compact index when it is an
-// evolving magnetic face (-1 otherwise).
-void touched_faces(const mm_ctx* c, std::vector<int>& idx, std::vector<unsigned char>& fam, std::vector<int>& mag) {
-  std::unordered_map<long long, int> evolving;
-  std::unordered_set<long long> done;
-  auto key = [&](int f, int pi) { return (long long)f * (long long)c->nelem + pi; };
-  for (int t = 0; t < c->nmag; ++t) evolving[key(c->h_fam[t], c->h_idx[t])] = t;
+// transverse neighbours), each once: the evolving faces first, entry t
+// holding face t (compact index t), then the other faces they read (-1).
+// Returns false if a neighbour falls outside the padded grid.
+bool touched_faces(const mm_ctx* c, std::vector<int>& idx, std::vector<unsigned char>& fam, std::vector<int>& mag) {
+  const size_t ne = c->nelem;
+  std::vector<uint64_t> seen((3 * ne + 63) / 64, 0);   // one bit per (family, padded index)
   auto dn = [&](int i, int n, bool p) { return (p && i == 0) ? n - 1 : i - 1; };
   auto up = [&](int i, int n, bool p) { return (p && i == n - 1) ? 0 : i + 1; };
   const bool pxp = c->per & 1, pyp = c->per & 2, pzp = c->per & 4;
-  auto add = [&](int f, int pi) {
-    const long long kk = key(f, pi);
-    if (!done.insert(kk).second) return;
-    idx.push_back(pi);
+  bool ok = true;
+  auto add = [&](int f, long long pi, int m) {
+    if (pi < 0 || (size_t)pi >= ne) {
+      ok = false;
+      return;
+    }
+    const size_t key = (size_t)f * ne + (size_t)pi;
+    uint64_t& word = seen[key >> 6];
+    const uint64_t bit = 1ull << (key & 63);
+    if (word & bit) return;
+    word |= bit;
+    idx.push_back((int)pi);
     fam.push_back((unsigned char)f);
-    auto it = evolving.find(kk);
-    mag.push_back(it == evolving.end() ? -1 : it->second);
+    mag.push_back(m);
+  };
+  const size_t nm = (size_t)c->nmag;
+  idx.reserve(4 * nm);
+  fam.reserve(4 * nm);
+  mag.reserve(4 * nm);
+  for (int t = 0; t < c->nmag; ++t) add(c->h_fam[t], c->h_idx[t], t);
+  auto P = [&](int a, int b2, int d2) {
+    return a < 0 || b2 < 0 || d2 < 0 ? -1ll : (long long)pidx(c, a, b2, d2);
   };
   for (int t = 0; t < c->nmag; ++t) {
     const int pi = c->h_idx[t], f = c->h_fam[t];
     const int k = pi / (c->px * c->py), rr = pi - k * c->px * c->py, j = rr / c->px, i = rr - j * c->px;
-    auto P = [&](int a, int b2, int d2) { return (int)pidx(c, a, b2, d2); };
-    add(f, pi);
     if (f == 0) {
       const int im = dn(i, c->nx, pxp), jp = up(j, c->ny, pyp), kp = up(k, c->nz, pzp);
-      add(1, P(im, j, k)); add(1, P(i, j, k)); add(1, P(im, jp, k)); add(1, P(i, jp, k));
-      add(2, P(im, j, k)); add(2, P(i, j, k)); add(2, P(im, j, kp)); add(2, P(i, j, kp));
+      add(1, P(im, j, k), -1); add(1, P(i, j, k), -1); add(1, P(im, jp, k), -1); add(1, P(i, jp, k), -1);
+      add(2, P(im, j, k), -1); add(2, P(i, j, k), -1); add(2, P(im, j, kp), -1); add(2, P(i, j, kp), -1);
     } else if (f == 1) {
       const int jm = dn(j, c->ny, pyp), ip = up(i, c->nx, pxp), kp = up(k, c->nz, pzp);
-      add(0, P(i, jm, k)); add(0, P(i, j, k)); add(0, P(ip, jm, k)); add(0, P(ip, j, k));
-      add(2, P(i, jm, k)); add(2, P(i, j, k)); add(2, P(i, jm, kp)); add(2, P(i, j, kp));
+      add(0, P(i, jm, k), -1); add(0, P(i, j, k), -1); add(0, P(ip, jm, k), -1); add(0, P(ip, j, k), -1);
+      add(2, P(i, jm, k), -1); add(2, P(i, j, k), -1); add(2, P(i, jm, kp), -1); add(2, P(i, j, kp), -1);
     } else {
       const int km = dn(k, c->nz, pzp), ip = up(i, c->nx, pxp), jp = up(j, c->ny, pyp);
-      add(0, P(i, j, km)); add(0, P(i, j, k)); add(0, P(ip, j, km)); add(0, P(ip, j, k));
-      add(1, P(i, j, km)); add(1, P(i, j, k)); add(1, P(i, jp, km)); add(1, P(i, jp, k));
+      add(0, P(i, j, km), -1); add(0, P(i, j, k), -1); add(0, P(ip, j, km), -1); add(0, P(ip, j, k), -1);
+      add(1, P(i, j, km), -1); add(1, P(i, j, k), -1); add(1, P(i, jp, km), -1); add(1, P(i, jp, k), -1);
     }
   }
+  return ok;
 }
 
 // Largest iteration count of the sub-steps run so far (the recompute repeats
@@ -244,7 +257,8 @@ mm_status adj_alloc(mm_ctx* c) {
     if (!w->qb || !w->hbit || !w->msf_b || !w->aoms_b) return fail(c, MM_ENOMEM, "adjoint work allocation failed");
     std::vector<int> ti, tm;
     std::vector<unsigned char> tf;
-    touched_faces(c, ti, tf, tm);
+    if (!touched_faces(c, ti, tf, tm))
+      return fail(c, MM_ESTATE, "adjoint: a magnetic face's neighbour lies outside the grid");
     w->nt = (int)ti.size();
     w->tidx = (int*)dalloc(c, ti.size() * 4);
     w->tfam = (unsigned char*)dalloc(c, tf.size());
@@ -314,9 +328,14 @@ T* arr3(const void* blk, const mm_ctx* c, int a) {
 }
 
 // Reverse of one H-M sub-step whose input was (Hs, Ms0), output H (Ho),
-// iterates `log` and count R.
+// iterates `log` and count R.  With defer, it stops before the curl
+// transpose: the caller runs it (inside adj_e_coef) and then adj_face_finish.
 template <typename T>
-mm_status adj_substep(mm_ctx* c, T* const* Hs, const double* Ms0, T* const* Ho, const double* log, int R) {
+mm_status adj_face_finish(mm_ctx* c);
+
+template <typename T>
+mm_status adj_substep(mm_ctx* c, T* const* Hs, const double* Ms0, T* const* Ho, const double* log, int R,
+                      bool defer = false) {
   AdjWork& w = *c->adjw;
   Geo g = make_geo(c);
   T* Eb[3] = {(T*)w.Eb[0], (T*)w.Eb[1], (T*)w.Eb[2]};
@@ -351,13 +370,28 @@ mm_status adj_substep(mm_ctx* c, T* const* Hs, const double* Ms0, T* const* Ho, 
   if (w.nt > 0)
     hipLaunchKernelGGL((mmk::adj_touch<T>), dim3(tb), dim3(256), 0, c->stream, g, w.tidx, w.tfam, w.nt, Hb[0],
                        Hb[1], Hb[2], Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], 0);
+  HIPCHECK(c, hipGetLastError());
+  if (defer) return MM_OK;
   dim3 grid;
   const int kc = kchunk_for(c, grid);
   hipLaunchKernelGGL((mmk::add_curl_h<T>), grid, dim3(64, 4), 0, c->stream, g, Eb[0], Eb[1], Eb[2],
                      (const T*)Hb[0], (const T*)Hb[1], (const T*)Hb[2], -0.5 * c->dt / mmk::kMu0, kc);
+  HIPCHECK(c, hipGetLastError());
+  return adj_face_finish<T>(c);
+}
+
+// After the curl transpose: Hb = T + Gb on the touched faces (Xb, Gb
+// cleared there) and the wall faces cleared.
+template <typename T>
+mm_status adj_face_finish(mm_ctx* c) {
+  AdjWork& w = *c->adjw;
+  const Geo g = make_geo(c);
+  T* Hb[3] = {(T*)w.Hb[0], (T*)w.Hb[1], (T*)w.Hb[2]};
+  T* Xb[3] = {(T*)w.Xb[0], (T*)w.Xb[1], (T*)w.Xb[2]};
+  T* Gb[3] = {(T*)w.Gb[0], (T*)w.Gb[1], (T*)w.Gb[2]};
   if (w.nt > 0)
-    hipLaunchKernelGGL((mmk::adj_touch<T>), dim3(tb), dim3(256), 0, c->stream, g, w.tidx, w.tfam, w.nt, Hb[0],
-                       Hb[1], Hb[2], Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], 1);
+    hipLaunchKernelGGL((mmk::adj_touch<T>), dim3((w.nt + 255) / 256), dim3(256), 0, c->stream, g, w.tidx, w.tfam,
+                       w.nt, Hb[0], Hb[1], Hb[2], Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], 1);
   const long long wall = std::max({(long long)c->ny * c->nz, (long long)c->nx * c->nz, (long long)c->nx * c->ny});
   hipLaunchKernelGGL((mmk::adj_zero_walls<T>), dim3((unsigned)((wall + 255) / 256), 3), dim3(256), 0, c->stream, g,
                      Hb[0], Hb[1], Hb[2]);
@@ -365,7 +399,9 @@ mm_status adj_substep(mm_ctx* c, T* const* Hs, const double* Ms0, T* const* Ho, 
   return MM_OK;
 }
 
-// Reverse of Step 2 of step c->step: En = E^n, Hh = H^{n+1/2}.
+// Reverse of Step 2 of step c->step: En = E^n, Hh = H^{n+1/2}.  It opens
+// with the curl transpose deferred by the Step 3 reverse before it (fused
+// into adj_e_coef) and that reverse's face finish.
 template <typename T>
 mm_status adj_estep(mm_ctx* c, const void* En, const void* Hh) {
   AdjWork& w = *c->adjw;
@@ -380,12 +416,17 @@ mm_status adj_estep(mm_ctx* c, const void* En, const void* Hh) {
     hipLaunchKernelGGL((mmk::adj_e_coef<T, true>), grid, dim3(64, 4), 0, c->stream, g, Eb[0], Eb[1], Eb[2],
                        arr3<T>(En, c, 0), arr3<T>(En, c, 1), arr3<T>(En, c, 2), arr3<T>(Hh, c, 0),
                        arr3<T>(Hh, c, 1), arr3<T>(Hh, c, 2), (const T*)c->eps, (const T*)c->sig, Wv[0], Wv[1],
-                       Wv[2], w.epsb[0], w.epsb[1], w.epsb[2], (T)c->dt, src, kc);
+                       Wv[2], w.epsb[0], w.epsb[1], w.epsb[2], (T)c->dt, src, (const T*)Hb[0],
+                       (const T*)Hb[1], (const T*)Hb[2], -0.5 * c->dt / mmk::kMu0, kc);
   else
     hipLaunchKernelGGL((mmk::adj_e_coef<T, false>), grid, dim3(64, 4), 0, c->stream, g, Eb[0], Eb[1], Eb[2],
                        arr3<T>(En, c, 0), arr3<T>(En, c, 1), arr3<T>(En, c, 2), arr3<T>(Hh, c, 0),
                        arr3<T>(Hh, c, 1), arr3<T>(Hh, c, 2), (const T*)c->eps, (const T*)c->sig, Wv[0], Wv[1],
-                       Wv[2], w.epsb[0], w.epsb[1], w.epsb[2], (T)c->dt, src, kc);
+                       Wv[2], w.epsb[0], w.epsb[1], w.epsb[2], (T)c->dt, src, (const T*)Hb[0],
+                       (const T*)Hb[1], (const T*)Hb[2], -0.5 * c->dt / mmk::kMu0, kc);
+  HIPCHECK(c, hipGetLastError());
+  mm_status fs = adj_face_finish<T>(c);
+  if (fs) return fs;
   // H_bar += curl E(W): the non-magnetic H kernel with coefficient -1
   hipLaunchKernelGGL((mmk::h_bulk<T, false, 1>), dim3(c->n_all), dim3(64, 4), 0, c->stream, g, Hb[0], Hb[1],
                      Hb[2], (const T*)Wv[0], (const T*)Wv[1], (const T*)Wv[2], (const T*)nullptr, (T)-1, (T)0,
@@ -462,7 +503,7 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
     }
     if ((s = adj_seed<T>(c, i0, (void* const*)E1, (void* const*)H1))) return s;
     // Step 3: input (H, M)^{n+1/2}, output H^{n+1}
-    if ((s = adj_substep<T>(c, Hh, w.sMh[j], H1, w.slog[j] + lsub, iters[2 * j + 1]))) return s;
+    if ((s = adj_substep<T>(c, Hh, w.sMh[j], H1, w.slog[j] + lsub, iters[2 * j + 1], true))) return s;
     // Step 2
     c->step = m0 + j;
     if ((s = adj_estep<T>(c, w.sE[j], w.sHh[j]))) return s;

@@ -406,6 +406,30 @@ __global__ __launch_bounds__(256) void copy_batch(CopyBatch b) {
     d[q] = s[q];
 }
 
+// Face values at a list of (family, padded index) entries, to (gather) or
+// from (scatter) a compact array: the per-step H^n storage of the
+// recompute, which the reverse reads only at the faces the magnetic rows
+// touch and on the flux plane's two H planes.
+template <typename T>
+__global__ __launch_bounds__(256) void list_gather(const int* __restrict__ idx, const unsigned char* __restrict__ fam,
+                                                  int n, const T* __restrict__ H0, const T* __restrict__ H1,
+                                                  const T* __restrict__ H2, T* __restrict__ out) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int f = fam[u];
+  out[u] = (f == 0 ? H0 : (f == 1 ? H1 : H2))[idx[u]];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void list_scatter(const int* __restrict__ idx,
+                                                   const unsigned char* __restrict__ fam, int n,
+                                                   const T* __restrict__ in, T* H0, T* H1, T* H2) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int f = fam[u];
+  (f == 0 ? H0 : (f == 1 ? H1 : H2))[idx[u]] = in[u];
+}
+
 // Reverse of Step 2 on every interior edge: with D = eps/dt + sigma/2,
 // ca = (eps/dt - sigma/2)/D, cb = 1/D:  d ca/d eps = (sigma/dt)/D^2,
 // d cb/d eps = -(1/dt)/D^2.  epsb accumulates E_bar (E^n d ca + (curl H - J g) d cb);

@@ -26,8 +26,16 @@ struct AdjWork {
   double* Q[9] = {};
   double** dQ = nullptr;
   double* epsb[3] = {};
-  std::vector<void*> sE, sH, sHh;
+  std::vector<void*> sE, sHc, sHh;   // sHc: H^n at the list entries only (compact)
   std::vector<double*> sM, sMh, slog;
+  // the list sHc holds: the touched faces, then the H_y, H_z faces of the
+  // flux plane's two H planes (for the plane at x node g_i0)
+  std::vector<int> h_tidx;
+  std::vector<unsigned char> h_tfam;
+  int* gidx = nullptr;
+  unsigned char* gfam = nullptr;
+  int ng = 0, gcap = 0, g_i0 = -1;
+  void* Hsc[2] = {};                 // full-size H scratch the compact steps are scattered into
   double *b[3] = {}, *d[3] = {}, *hes[3] = {}, *bb[3] = {}, *db[3] = {}, *Mb[3] = {};
   double *qb = nullptr, *hbit = nullptr, *msf_b = nullptr, *aoms_b = nullptr;
   int* tidx = nullptr;
@@ -267,7 +275,15 @@ mm_status adj_alloc(mm_ctx* c) {
     HIPCHECK(c, hipMemcpy(w->tidx, ti.data(), ti.size() * 4, hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(w->tfam, tf.data(), tf.size(), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(w->tmag, tm.data(), tm.size() * 4, hipMemcpyHostToDevice));
+    w->h_tidx = std::move(ti);
+    w->h_tfam = std::move(tf);
   }
+  w->gcap = (int)w->h_tidx.size() + 4 * nodes(c, 1) * nodes(c, 2);
+  w->gidx = (int*)dalloc(c, (size_t)w->gcap * sizeof(int));
+  w->gfam = (unsigned char*)dalloc(c, (size_t)w->gcap);
+  w->Hsc[0] = dalloc(c, 3 * fb);
+  w->Hsc[1] = dalloc(c, 3 * fb);
+  if (!w->gidx || !w->gfam || !w->Hsc[0] || !w->Hsc[1]) return fail(c, MM_ENOMEM, "adjoint work allocation failed");
   for (int q = 1; q * w->K2 < w->K; ++q) {
     void* blk = dalloc(c, state_bytes(c));
     if (!blk) return fail(c, MM_ENOMEM, "inner checkpoint allocation failed");
@@ -275,14 +291,14 @@ mm_status adj_alloc(mm_ctx* c) {
   }
   for (int j = 0; j < w->K2; ++j) {
     void* e = dalloc(c, 3 * fb);
-    void* h = dalloc(c, 3 * fb);
+    void* h = dalloc(c, (size_t)w->gcap * c->esz);
     void* hh = dalloc(c, 3 * fb);
     double* m = (double*)dalloc(c, 3 * ntot * 8);
     double* mh = (double*)dalloc(c, 3 * ntot * 8);
     double* lg = (double*)dalloc(c, 2 * (size_t)w->cap * nm * 8);
     if (!e || !h || !hh || !m || !mh || !lg) return fail(c, MM_ENOMEM, "adjoint segment storage allocation failed");
     w->sE.push_back(e);
-    w->sH.push_back(h);
+    w->sHc.push_back(h);
     w->sHh.push_back(hh);
     w->sM.push_back(m);
     w->sMh.push_back(mh);
@@ -447,9 +463,50 @@ mm_status adj_seed(mm_ctx* c, int i0, void* const* E1, void* const* H1) {
   return MM_OK;
 }
 
+// The compact H list for the flux plane at x node i0: the touched faces,
+// then the H_y and H_z faces of the planes i0 - 1 and i0 (every (j, k) node
+// the seed reads), each once.
+mm_status adj_list(mm_ctx* c, int i0) {
+  AdjWork& w = *c->adjw;
+  if (w.g_i0 == i0) return MM_OK;
+  const size_t ne = c->nelem;
+  std::vector<uint64_t> seen((3 * ne + 63) / 64, 0);
+  std::vector<int> gi;
+  std::vector<unsigned char> gf;
+  gi.reserve(w.gcap);
+  gf.reserve(w.gcap);
+  auto add = [&](int f, size_t pi) {
+    const size_t key = (size_t)f * ne + pi;
+    uint64_t& word = seen[key >> 6];
+    const uint64_t bit = 1ull << (key & 63);
+    if (word & bit) return;
+    word |= bit;
+    gi.push_back((int)pi);
+    gf.push_back((unsigned char)f);
+  };
+  for (size_t u = 0; u < w.h_tidx.size(); ++u) add(w.h_tfam[u], (size_t)w.h_tidx[u]);
+  const int NY = nodes(c, 1), NZ = nodes(c, 2);
+  const int im = (c->per & 1) ? (i0 == 0 ? c->nx - 1 : i0 - 1) : i0 - 1;
+  for (int pl : {im, i0})
+    for (int k = 0; k < NZ; ++k)
+      for (int j = 0; j < NY; ++j) {
+        add(1, pidx(c, pl, j, k));
+        add(2, pidx(c, pl, j, k));
+      }
+  if (gi.size() > (size_t)w.gcap) return fail(c, MM_ESTATE, "adjoint: the compact H list overflows");
+  if (!gi.empty()) {
+    HIPCHECK(c, hipMemcpy(w.gidx, gi.data(), gi.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(w.gfam, gf.data(), gf.size(), hipMemcpyHostToDevice));
+  }
+  w.ng = (int)gi.size();
+  w.g_i0 = i0;
+  return MM_OK;
+}
+
 // Steps [m0, m0 + len): restore the state saved at m0, recompute the span
-// storing per step E^n, H^n, M^n, H^{n+1/2}, M^{n+1/2} and the iterate logs,
-// then reverse its steps, last first, into the cotangents.
+// storing per step E^n, H^n (at the list entries), M^n, H^{n+1/2},
+// M^{n+1/2} and the iterate logs, then reverse its steps, last first, into
+// the cotangents.
 template <typename T>
 mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
   AdjWork& w = *c->adjw;
@@ -463,9 +520,13 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
     {
       CopyList L;
       add3(c, L, w.sE[j], c->E, true);
-      add3(c, L, w.sH[j], c->H, true);
       addM(c, L, w.sM[j], true);
       if ((s = run_copies(c, L))) return s;
+    }
+    if (w.ng > 0) {
+      hipLaunchKernelGGL((mmk::list_gather<T>), dim3((w.ng + 255) / 256), dim3(256), 0, c->stream, w.gidx, w.gfam,
+                         w.ng, (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], (T*)w.sHc[j]);
+      HIPCHECK(c, hipGetLastError());
     }
     c->hlog_cur = w.slog[j];
     if ((s = substep<T>(c))) return s;
@@ -490,16 +551,23 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
   HIPCHECK(c, hipMemcpy(&ew, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
   if (ew & 8) return fail(c, MM_ESTATE, "a sub-step needed more iterations than the adjoint log holds (%d)", w.cap);
   for (int j = len - 1; j >= 0; --j) {
-    // level n+1: the next stored step, or the live fields after the span's last step
+    // H^n of step j into scratch j % 2 (valid at the list entries); H^{n+1}
+    // is the other scratch, filled for step j + 1, or the live fields after
+    // the span's last step
     T* E1[3];
     T* H1[3];
     T* Hh[3];
     T* Hn[3];
     for (int a = 0; a < 3; ++a) {
       E1[a] = j + 1 < len ? arr3<T>(w.sE[j + 1], c, a) : (T*)c->E[a];
-      H1[a] = j + 1 < len ? arr3<T>(w.sH[j + 1], c, a) : (T*)c->H[a];
+      H1[a] = j + 1 < len ? arr3<T>(w.Hsc[(j + 1) & 1], c, a) : (T*)c->H[a];
       Hh[a] = arr3<T>(w.sHh[j], c, a);
-      Hn[a] = arr3<T>(w.sH[j], c, a);
+      Hn[a] = arr3<T>(w.Hsc[j & 1], c, a);
+    }
+    if (w.ng > 0) {
+      hipLaunchKernelGGL((mmk::list_scatter<T>), dim3((w.ng + 255) / 256), dim3(256), 0, c->stream, w.gidx, w.gfam,
+                         w.ng, (const T*)w.sHc[j], Hn[0], Hn[1], Hn[2]);
+      HIPCHECK(c, hipGetLastError());
     }
     if ((s = adj_seed<T>(c, i0, (void* const*)E1, (void* const*)H1))) return s;
     // Step 3: input (H, M)^{n+1/2}, output H^{n+1}
@@ -516,6 +584,7 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
 template <typename T>
 mm_status adjoint_run(mm_ctx* c, int i0, double* grad_eps, double* grad_Ms) {
   mm_status s = adj_alloc(c);
+  if (!s) s = adj_list(c, i0);
   if (s) return s;
   AdjWork& w = *c->adjw;
   const size_t fb = c->nelem * c->esz, fd = c->nelem * sizeof(double);

@@ -433,19 +433,23 @@ __global__ __launch_bounds__(256) void list_scatter(const int* __restrict__ idx,
 // Reverse of Step 2 on every interior edge: with D = eps/dt + sigma/2,
 // ca = (eps/dt - sigma/2)/D, cb = 1/D:  d ca/d eps = (sigma/dt)/D^2,
 // d cb/d eps = -(1/dt)/D^2.  epsb accumulates E_bar (E^n d ca + (curl H - J g) d cb);
-// W = cb E_bar (to H through curl E), E_bar <- ca E_bar.  First, the curl
-// transpose of the Step 3 reverse that precedes it: E_bar += curl H(C) with
-// C = cscale * Cf (the same per-edge expression as add_curl_h).
+// W = cb E_bar (to H through curl E), E_bar <- ca E_bar.  The forward set
+// E^{n+1} = ca E^n + cb (curl H - J g), so curl H - J g is taken back from
+// the two stored E levels as (E^{n+1} - ca E^n) / cb in FP64 (ca and cb are
+// the forward's own values, bit for bit; the difference carries the
+// forward's rounding, a few ulp of E).  First, the curl transpose of the
+// Step 3 reverse that precedes it: E_bar += curl H(C) with C = cscale * Cf
+// (the same per-edge expression as add_curl_h).
 template <typename T, bool SIG>
 __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T* __restrict__ Eb1,
                                                  T* __restrict__ Eb2, const T* __restrict__ En0,
                                                  const T* __restrict__ En1, const T* __restrict__ En2,
-                                                 const T* __restrict__ Hx, const T* __restrict__ Hy,
-                                                 const T* __restrict__ Hz, const T* __restrict__ eps,
+                                                 const T* __restrict__ Ea0, const T* __restrict__ Ea1,
+                                                 const T* __restrict__ Ea2, const T* __restrict__ eps,
                                                  const T* __restrict__ sig, T* __restrict__ W0, T* __restrict__ W1,
                                                  T* __restrict__ W2, double* __restrict__ epsb0,
                                                  double* __restrict__ epsb1, double* __restrict__ epsb2, T dt,
-                                                 Src src, const T* __restrict__ Cf0, const T* __restrict__ Cf1,
+                                                 const T* __restrict__ Cf0, const T* __restrict__ Cf1,
                                                  const T* __restrict__ Cf2, double cscale, int kchunk) {
   const int i = blockIdx.x * 64 + threadIdx.x;
   const int j = blockIdx.y * 4 + threadIdx.y;
@@ -459,12 +463,10 @@ __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T*
   const T idx = (T)g.idx, idy = (T)g.idy, idz = (T)g.idz;
   const T sdx = (T)g.dx, sdy = (T)g.dy, sdz = (T)g.dz;
   const T e0 = (T)kEps0, half = (T)0.5, quarter = (T)0.25;
-  T hx_km = 0, hy_km = 0, e_km = 0, e_jm_km = 0, e_im_km = 0, s_km = 0, s_jm_km = 0, s_im_km = 0;
+  T e_km = 0, e_jm_km = 0, e_im_km = 0, s_km = 0, s_jm_km = 0, s_im_km = 0;
   T wx_km = 0, wy_km = 0;
   if (pzp || k0 >= 1) {
     const int km = dn(k0, g.nz, pzp);
-    hx_km = Hx[at(g, i, j, km)];
-    hy_km = Hy[at(g, i, j, km)];
     wx_km = (T)(cscale * D(Cf0[at(g, i, j, km)]));
     wy_km = (T)(cscale * D(Cf1[at(g, i, j, km)]));
     e_km = eps[at(g, i, j, km)];
@@ -480,8 +482,6 @@ __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T*
     const bool kin = pzp || k >= 1;
     const int c = at(g, i, j, k);
     const int cjm = at(g, i, jm, k), cim = at(g, im, j, k);
-    const T hx = Hx[c], hy = Hy[c], hz = Hz[c];
-    const T hz_jm = Hz[cjm], hx_jm = Hx[cjm], hz_im = Hz[cim], hy_im = Hy[cim];
     const T wx = (T)(cscale * D(Cf0[c])), wy = (T)(cscale * D(Cf1[c])), wz = (T)(cscale * D(Cf2[c]));
     const T wz_jm = (T)(cscale * D(Cf2[cjm])), wx_jm = (T)(cscale * D(Cf0[cjm]));
     const T wz_im = (T)(cscale * D(Cf2[cim])), wy_im = (T)(cscale * D(Cf1[cim]));
@@ -493,8 +493,8 @@ __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T*
       s_im = sig[cim];
       s_imjm = sig[at(g, im, jm, k)];
     }
-    // one edge: given the 4-cell sums, the curl and the cotangent
-    auto edge = [&](bool in, T esum, T ssum, T curl, T en, T& eb, T& w, double& epsb) {
+    // one edge: given the 4-cell sums and the two E levels, the cotangent
+    auto edge = [&](bool in, T esum, T ssum, T en, T e1, T& eb, T& w, double& epsb) {
       if (!in) {
         w = (T)0;
         return;
@@ -506,52 +506,45 @@ __global__ __launch_bounds__(256) void adj_e_coef(Geo g, T* __restrict__ Eb0, T*
       const T den = a + b;
       const T ca = SIG ? (a - b) / den : (T)1;
       const T cb = (T)1 / den;
+      const double curl = (D(e1) - D(ca) * D(en)) / D(cb);
       const double d2 = D(den) * D(den);
       const double dca = SIG ? (D(sg) / D(dt)) / d2 : 0.0;
       const double dcb = -(1.0 / D(dt)) / d2;
       const double ebv = D(eb);
-      epsb += ebv * (D(en) * dca + D(curl) * dcb);
+      epsb += ebv * (D(en) * dca + curl * dcb);
       w = cb * eb;
       eb = ca * eb;
     };
     {
-      T curl = dq(hz - hz_jm, sdy, idy) - dq(hy - hy_km, sdz, idz);
-      if (src.comp == 0) curl = curl - (T)src_term(src, 0, i, j, k);
       T eb = Eb0[c], w;
       if (jin && kin) eb = eb + (dq(wz - wz_jm, sdy, idy) - dq(wy - wy_km, sdz, idz));
       double eps_acc = epsb0[c];
-      edge(jin && kin, (e_jm_km + e_km) + (e_jm + e_c), (s_jm_km + s_km) + (s_jm + s_c), curl, En0[c], eb, w,
+      edge(jin && kin, (e_jm_km + e_km) + (e_jm + e_c), (s_jm_km + s_km) + (s_jm + s_c), En0[c], Ea0[c], eb, w,
            eps_acc);
       Eb0[c] = eb;
       W0[c] = w;
       epsb0[c] = eps_acc;
     }
     {
-      T curl = dq(hx - hx_km, sdz, idz) - dq(hz - hz_im, sdx, idx);
-      if (src.comp == 1) curl = curl - (T)src_term(src, 1, i, j, k);
       T eb = Eb1[c], w;
       if (iin && kin) eb = eb + (dq(wx - wx_km, sdz, idz) - dq(wz - wz_im, sdx, idx));
       double eps_acc = epsb1[c];
-      edge(iin && kin, (e_im_km + e_km) + (e_im + e_c), (s_im_km + s_km) + (s_im + s_c), curl, En1[c], eb, w,
+      edge(iin && kin, (e_im_km + e_km) + (e_im + e_c), (s_im_km + s_km) + (s_im + s_c), En1[c], Ea1[c], eb, w,
            eps_acc);
       Eb1[c] = eb;
       W1[c] = w;
       epsb1[c] = eps_acc;
     }
     {
-      T curl = dq(hy - hy_im, sdx, idx) - dq(hx - hx_jm, sdy, idy);
-      if (src.comp == 2) curl = curl - (T)src_term(src, 2, i, j, k);
       T eb = Eb2[c], w;
       if (iin && jin) eb = eb + (dq(wy - wy_im, sdx, idx) - dq(wx - wx_jm, sdy, idy));
       double eps_acc = epsb2[c];
-      edge(iin && jin, (e_imjm + e_jm) + (e_im + e_c), (s_imjm + s_jm) + (s_im + s_c), curl, En2[c], eb, w,
+      edge(iin && jin, (e_imjm + e_jm) + (e_im + e_c), (s_imjm + s_jm) + (s_im + s_c), En2[c], Ea2[c], eb, w,
            eps_acc);
       Eb2[c] = eb;
       W2[c] = w;
       epsb2[c] = eps_acc;
     }
-    hx_km = hx;
-    hy_km = hy;
     wx_km = wx;
     wy_km = wy;
     e_km = e_c;

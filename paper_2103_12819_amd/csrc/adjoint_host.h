@@ -26,7 +26,7 @@ struct AdjWork {
   double* Q[9] = {};
   double** dQ = nullptr;
   double* epsb[3] = {};
-  std::vector<void*> sE, sHc, sHh;   // sHc: H^n at the list entries only (compact)
+  std::vector<void*> sE, sHc, sHh;   // sHc, sHh: H^n, H^{n+1/2} at the list entries only (compact)
   std::vector<double*> sM, sMh, slog;
   // the list sHc holds: the touched faces, then the H_y, H_z faces of the
   // flux plane's two H planes (for the plane at x node g_i0)
@@ -35,7 +35,7 @@ struct AdjWork {
   int* gidx = nullptr;
   unsigned char* gfam = nullptr;
   int ng = 0, gcap = 0, g_i0 = -1;
-  void* Hsc[2] = {};                 // full-size H scratch the compact steps are scattered into
+  void* Hsc[3] = {};                 // full-size H scratch the compact levels are scattered into
   double *b[3] = {}, *d[3] = {}, *hes[3] = {}, *bb[3] = {}, *db[3] = {}, *Mb[3] = {};
   double *qb = nullptr, *hbit = nullptr, *msf_b = nullptr, *aoms_b = nullptr;
   int* tidx = nullptr;
@@ -281,9 +281,11 @@ mm_status adj_alloc(mm_ctx* c) {
   w->gcap = (int)w->h_tidx.size() + 4 * nodes(c, 1) * nodes(c, 2);
   w->gidx = (int*)dalloc(c, (size_t)w->gcap * sizeof(int));
   w->gfam = (unsigned char*)dalloc(c, (size_t)w->gcap);
-  w->Hsc[0] = dalloc(c, 3 * fb);
-  w->Hsc[1] = dalloc(c, 3 * fb);
-  if (!w->gidx || !w->gfam || !w->Hsc[0] || !w->Hsc[1]) return fail(c, MM_ENOMEM, "adjoint work allocation failed");
+  for (void*& p : w->Hsc) {
+    p = dalloc(c, 3 * fb);
+    if (!p) return fail(c, MM_ENOMEM, "adjoint work allocation failed");
+  }
+  if (!w->gidx || !w->gfam) return fail(c, MM_ENOMEM, "adjoint work allocation failed");
   for (int q = 1; q * w->K2 < w->K; ++q) {
     void* blk = dalloc(c, state_bytes(c));
     if (!blk) return fail(c, MM_ENOMEM, "inner checkpoint allocation failed");
@@ -292,7 +294,7 @@ mm_status adj_alloc(mm_ctx* c) {
   for (int j = 0; j < w->K2; ++j) {
     void* e = dalloc(c, 3 * fb);
     void* h = dalloc(c, (size_t)w->gcap * c->esz);
-    void* hh = dalloc(c, 3 * fb);
+    void* hh = dalloc(c, (size_t)w->gcap * c->esz);
     double* m = (double*)dalloc(c, 3 * ntot * 8);
     double* mh = (double*)dalloc(c, 3 * ntot * 8);
     double* lg = (double*)dalloc(c, 2 * (size_t)w->cap * nm * 8);
@@ -415,31 +417,30 @@ mm_status adj_face_finish(mm_ctx* c) {
   return MM_OK;
 }
 
-// Reverse of Step 2 of step c->step: En = E^n, Hh = H^{n+1/2}.  It opens
-// with the curl transpose deferred by the Step 3 reverse before it (fused
-// into adj_e_coef) and that reverse's face finish.
+// Reverse of Step 2 of step c->step: En = E^n (a block), E1 = E^{n+1}.  It
+// opens with the curl transpose deferred by the Step 3 reverse before it
+// (fused into adj_e_coef) and that reverse's face finish.
 template <typename T>
-mm_status adj_estep(mm_ctx* c, const void* En, const void* Hh) {
+mm_status adj_estep(mm_ctx* c, const void* En, T* const* E1) {
   AdjWork& w = *c->adjw;
   Geo g = make_geo(c);
   dim3 grid;
   const int kc = kchunk_for(c, grid);
-  const mmk::Src src = make_src(c);
   T* Eb[3] = {(T*)w.Eb[0], (T*)w.Eb[1], (T*)w.Eb[2]};
   T* Hb[3] = {(T*)w.Hb[0], (T*)w.Hb[1], (T*)w.Hb[2]};
   T* Wv[3] = {(T*)w.W[0], (T*)w.W[1], (T*)w.W[2]};
   if (c->sig)
     hipLaunchKernelGGL((mmk::adj_e_coef<T, true>), grid, dim3(64, 4), 0, c->stream, g, Eb[0], Eb[1], Eb[2],
-                       arr3<T>(En, c, 0), arr3<T>(En, c, 1), arr3<T>(En, c, 2), arr3<T>(Hh, c, 0),
-                       arr3<T>(Hh, c, 1), arr3<T>(Hh, c, 2), (const T*)c->eps, (const T*)c->sig, Wv[0], Wv[1],
-                       Wv[2], w.epsb[0], w.epsb[1], w.epsb[2], (T)c->dt, src, (const T*)Hb[0],
-                       (const T*)Hb[1], (const T*)Hb[2], -0.5 * c->dt / mmk::kMu0, kc);
+                       arr3<T>(En, c, 0), arr3<T>(En, c, 1), arr3<T>(En, c, 2), (const T*)E1[0],
+                       (const T*)E1[1], (const T*)E1[2], (const T*)c->eps, (const T*)c->sig, Wv[0], Wv[1],
+                       Wv[2], w.epsb[0], w.epsb[1], w.epsb[2], (T)c->dt, (const T*)Hb[0], (const T*)Hb[1],
+                       (const T*)Hb[2], -0.5 * c->dt / mmk::kMu0, kc);
   else
     hipLaunchKernelGGL((mmk::adj_e_coef<T, false>), grid, dim3(64, 4), 0, c->stream, g, Eb[0], Eb[1], Eb[2],
-                       arr3<T>(En, c, 0), arr3<T>(En, c, 1), arr3<T>(En, c, 2), arr3<T>(Hh, c, 0),
-                       arr3<T>(Hh, c, 1), arr3<T>(Hh, c, 2), (const T*)c->eps, (const T*)c->sig, Wv[0], Wv[1],
-                       Wv[2], w.epsb[0], w.epsb[1], w.epsb[2], (T)c->dt, src, (const T*)Hb[0],
-                       (const T*)Hb[1], (const T*)Hb[2], -0.5 * c->dt / mmk::kMu0, kc);
+                       arr3<T>(En, c, 0), arr3<T>(En, c, 1), arr3<T>(En, c, 2), (const T*)E1[0],
+                       (const T*)E1[1], (const T*)E1[2], (const T*)c->eps, (const T*)c->sig, Wv[0], Wv[1],
+                       Wv[2], w.epsb[0], w.epsb[1], w.epsb[2], (T)c->dt, (const T*)Hb[0], (const T*)Hb[1],
+                       (const T*)Hb[2], -0.5 * c->dt / mmk::kMu0, kc);
   HIPCHECK(c, hipGetLastError());
   mm_status fs = adj_face_finish<T>(c);
   if (fs) return fs;
@@ -504,8 +505,8 @@ mm_status adj_list(mm_ctx* c, int i0) {
 }
 
 // Steps [m0, m0 + len): restore the state saved at m0, recompute the span
-// storing per step E^n, H^n (at the list entries), M^n, H^{n+1/2},
-// M^{n+1/2} and the iterate logs, then reverse its steps, last first, into
+// storing per step E^n, M^n, M^{n+1/2}, the iterate logs and, at the list
+// entries only, H^n and H^{n+1/2}; then reverse its steps, last first, into
 // the cotangents.
 template <typename T>
 mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
@@ -532,9 +533,13 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
     if ((s = substep<T>(c))) return s;
     {
       CopyList L;
-      add3(c, L, w.sHh[j], c->H, true);
       addM(c, L, w.sMh[j], true);
       if ((s = run_copies(c, L))) return s;
+    }
+    if (w.ng > 0) {
+      hipLaunchKernelGGL((mmk::list_gather<T>), dim3((w.ng + 255) / 256), dim3(256), 0, c->stream, w.gidx, w.gfam,
+                         w.ng, (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], (T*)w.sHh[j]);
+      HIPCHECK(c, hipGetLastError());
     }
     if ((s = e_step<T>(c))) return s;
     c->hlog_cur = w.slog[j] + lsub;
@@ -561,12 +566,14 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
     for (int a = 0; a < 3; ++a) {
       E1[a] = j + 1 < len ? arr3<T>(w.sE[j + 1], c, a) : (T*)c->E[a];
       H1[a] = j + 1 < len ? arr3<T>(w.Hsc[(j + 1) & 1], c, a) : (T*)c->H[a];
-      Hh[a] = arr3<T>(w.sHh[j], c, a);
+      Hh[a] = arr3<T>(w.Hsc[2], c, a);
       Hn[a] = arr3<T>(w.Hsc[j & 1], c, a);
     }
     if (w.ng > 0) {
       hipLaunchKernelGGL((mmk::list_scatter<T>), dim3((w.ng + 255) / 256), dim3(256), 0, c->stream, w.gidx, w.gfam,
                          w.ng, (const T*)w.sHc[j], Hn[0], Hn[1], Hn[2]);
+      hipLaunchKernelGGL((mmk::list_scatter<T>), dim3((w.ng + 255) / 256), dim3(256), 0, c->stream, w.gidx, w.gfam,
+                         w.ng, (const T*)w.sHh[j], Hh[0], Hh[1], Hh[2]);
       HIPCHECK(c, hipGetLastError());
     }
     if ((s = adj_seed<T>(c, i0, (void* const*)E1, (void* const*)H1))) return s;
@@ -574,7 +581,7 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
     if ((s = adj_substep<T>(c, Hh, w.sMh[j], H1, w.slog[j] + lsub, iters[2 * j + 1], true))) return s;
     // Step 2
     c->step = m0 + j;
-    if ((s = adj_estep<T>(c, w.sE[j], w.sHh[j]))) return s;
+    if ((s = adj_estep<T>(c, w.sE[j], E1))) return s;
     // Step 1: input (H, M)^n, output H^{n+1/2}
     if ((s = adj_substep<T>(c, Hn, w.sM[j], Hh, w.slog[j], iters[2 * j]))) return s;
   }

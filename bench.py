@@ -347,7 +347,7 @@ def run_adjoint_cost(steps=4000, ckpt=100):
             "max_abs_grad_Ms": float(np.abs(gm).max())}
 
 
-def run_scale(steps=500, ckpt=100, inner=10):
+def run_scale(steps=500, ckpt=100, inner=34):
     """The 1024x512x512 grid (268M cells) in FP32: forward `steps` steps with
     two-level adjoint checkpoints, then the adjoint of the time-integrated
     flux; per-kernel times of the first 100 forward steps, the forward rate

@@ -26,7 +26,10 @@ struct AdjWork {
   double* Q[9] = {};
   double** dQ = nullptr;
   double* epsb[3] = {};
-  std::vector<void*> sE, sHc, sHh;   // sHc, sHh: H^n, H^{n+1/2} at the list entries only (compact)
+  // per step j of a span: sE[j] = E^{n+1} (written there by the out-of-place
+  // E update; E^n of step 0 stays in the live E); sHc, sHh: H^n, H^{n+1/2}
+  // at the list entries only (compact)
+  std::vector<void*> sE, sHc, sHh;
   std::vector<double*> sM, sMh, slog;
   // the list sHc holds: the touched faces, then the H_y, H_z faces of the
   // flux plane's two H planes (for the plane at x node g_i0)
@@ -417,11 +420,11 @@ mm_status adj_face_finish(mm_ctx* c) {
   return MM_OK;
 }
 
-// Reverse of Step 2 of step c->step: En = E^n (a block), E1 = E^{n+1}.  It
-// opens with the curl transpose deferred by the Step 3 reverse before it
-// (fused into adj_e_coef) and that reverse's face finish.
+// Reverse of Step 2 of step c->step: En = E^n, E1 = E^{n+1}.  It opens
+// with the curl transpose deferred by the Step 3 reverse before it (fused
+// into adj_e_coef) and that reverse's face finish.
 template <typename T>
-mm_status adj_estep(mm_ctx* c, const void* En, T* const* E1) {
+mm_status adj_estep(mm_ctx* c, T* const* En, T* const* E1) {
   AdjWork& w = *c->adjw;
   Geo g = make_geo(c);
   dim3 grid;
@@ -431,13 +434,13 @@ mm_status adj_estep(mm_ctx* c, const void* En, T* const* E1) {
   T* Wv[3] = {(T*)w.W[0], (T*)w.W[1], (T*)w.W[2]};
   if (c->sig)
     hipLaunchKernelGGL((mmk::adj_e_coef<T, true>), grid, dim3(64, 4), 0, c->stream, g, Eb[0], Eb[1], Eb[2],
-                       arr3<T>(En, c, 0), arr3<T>(En, c, 1), arr3<T>(En, c, 2), (const T*)E1[0],
+                       (const T*)En[0], (const T*)En[1], (const T*)En[2], (const T*)E1[0],
                        (const T*)E1[1], (const T*)E1[2], (const T*)c->eps, (const T*)c->sig, Wv[0], Wv[1],
                        Wv[2], w.epsb[0], w.epsb[1], w.epsb[2], (T)c->dt, (const T*)Hb[0], (const T*)Hb[1],
                        (const T*)Hb[2], -0.5 * c->dt / mmk::kMu0, kc);
   else
     hipLaunchKernelGGL((mmk::adj_e_coef<T, false>), grid, dim3(64, 4), 0, c->stream, g, Eb[0], Eb[1], Eb[2],
-                       arr3<T>(En, c, 0), arr3<T>(En, c, 1), arr3<T>(En, c, 2), (const T*)E1[0],
+                       (const T*)En[0], (const T*)En[1], (const T*)En[2], (const T*)E1[0],
                        (const T*)E1[1], (const T*)E1[2], (const T*)c->eps, (const T*)c->sig, Wv[0], Wv[1],
                        Wv[2], w.epsb[0], w.epsb[1], w.epsb[2], (T)c->dt, (const T*)Hb[0], (const T*)Hb[1],
                        (const T*)Hb[2], -0.5 * c->dt / mmk::kMu0, kc);
@@ -504,23 +507,36 @@ mm_status adj_list(mm_ctx* c, int i0) {
   return MM_OK;
 }
 
+// The live E pointers, put back when this goes out of scope.
+struct KeepE {
+  mm_ctx* c;
+  void* E[3];
+  explicit KeepE(mm_ctx* ctx) : c(ctx) {
+    for (int a = 0; a < 3; ++a) E[a] = c->E[a];
+  }
+  ~KeepE() {
+    for (int a = 0; a < 3; ++a) c->E[a] = E[a];
+  }
+};
+
 // Steps [m0, m0 + len): restore the state saved at m0, recompute the span
-// storing per step E^n, M^n, M^{n+1/2}, the iterate logs and, at the list
-// entries only, H^n and H^{n+1/2}; then reverse its steps, last first, into
-// the cotangents.
+// storing per step E^{n+1} (the E update writes it straight into sE[j] and
+// the step goes on from there), M^n, M^{n+1/2}, the iterate logs and, at
+// the list entries only, H^n and H^{n+1/2}; then reverse its steps, last
+// first, into the cotangents.  E^{m0} stays in the live E arrays.
 template <typename T>
 mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
   AdjWork& w = *c->adjw;
   const size_t lsub = (size_t)w.cap * std::max(c->nmag, 1);
   mm_status s = copy_state(c, start, false);
   if (s) return s;
+  KeepE live(c);
   c->step = m0;
   c->substep = (int)(2 * m0);
   c->adj_recompute = true;
   for (int j = 0; j < len; ++j) {
     {
       CopyList L;
-      add3(c, L, w.sE[j], c->E, true);
       addM(c, L, w.sM[j], true);
       if ((s = run_copies(c, L))) return s;
     }
@@ -541,11 +557,14 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
                          w.ng, (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], (T*)w.sHh[j]);
       HIPCHECK(c, hipGetLastError());
     }
-    if ((s = e_step<T>(c))) return s;
+    void* eo[3] = {arr3<T>(w.sE[j], c, 0), arr3<T>(w.sE[j], c, 1), arr3<T>(w.sE[j], c, 2)};
+    if ((s = e_step<T>(c, eo))) return s;
+    for (int a = 0; a < 3; ++a) c->E[a] = eo[a];
     c->hlog_cur = w.slog[j] + lsub;
     if ((s = substep<T>(c))) return s;
     c->step++;
   }
+  for (int a = 0; a < 3; ++a) c->E[a] = live.E[a];
   c->hlog_cur = nullptr;
   c->adj_recompute = false;
   HIPCHECK(c, hipStreamSynchronize(c->stream));
@@ -563,8 +582,10 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
     T* H1[3];
     T* Hh[3];
     T* Hn[3];
+    T* En[3];
     for (int a = 0; a < 3; ++a) {
-      E1[a] = j + 1 < len ? arr3<T>(w.sE[j + 1], c, a) : (T*)c->E[a];
+      En[a] = j > 0 ? arr3<T>(w.sE[j - 1], c, a) : (T*)live.E[a];
+      E1[a] = arr3<T>(w.sE[j], c, a);
       H1[a] = j + 1 < len ? arr3<T>(w.Hsc[(j + 1) & 1], c, a) : (T*)c->H[a];
       Hh[a] = arr3<T>(w.Hsc[2], c, a);
       Hn[a] = arr3<T>(w.Hsc[j & 1], c, a);
@@ -581,7 +602,7 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
     if ((s = adj_substep<T>(c, Hh, w.sMh[j], H1, w.slog[j] + lsub, iters[2 * j + 1], true))) return s;
     // Step 2
     c->step = m0 + j;
-    if ((s = adj_estep<T>(c, w.sE[j], E1))) return s;
+    if ((s = adj_estep<T>(c, En, E1))) return s;
     // Step 1: input (H, M)^n, output H^{n+1/2}
     if ((s = adj_substep<T>(c, Hn, w.sM[j], Hh, w.slog[j], iters[2 * j]))) return s;
   }
@@ -611,6 +632,13 @@ mm_status adjoint_run(mm_ctx* c, int i0, double* grad_eps, double* grad_Ms) {
   }
   s = copy_state(c, w.fin, true);
   if (s) return s;
+  // the E slots: the edges the E update never writes (PEC walls) keep their
+  // constant values, so every slot starts as a copy of the live E
+  for (void* blk : w.sE) {
+    CopyList L;
+    add3(c, L, blk, c->E, true);
+    if ((s = run_copies(c, L))) return s;
+  }
   const long nseg = (N + K - 1) / K;
   const int K2 = w.K2;
   for (long sg = nseg - 1; sg >= 0; --sg) {

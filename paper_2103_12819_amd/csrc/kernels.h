@@ -133,13 +133,16 @@ __device__ __forceinline__ double src_term(const Src& s, int comp, int i, int j,
 // MAT: the cell maps come as a byte material id per cell and a table of
 // (eps_r, sigma) per id (exactly the values of the dense maps), staged in
 // LDS: 1 byte per cell instead of two map values.
-template <typename T, bool SIG, bool MAT, int RY = 4>
+// OOP: E^{n+1} goes to (Ox, Oy, Oz) and E^n stays in (Ex, Ey, Ez) (the
+// adjoint's recompute keeps every level); only interior edges are written.
+template <typename T, bool SIG, bool MAT, int RY = 4, bool OOP = false>
 __global__ __launch_bounds__(64 * RY) void e_update(Geo g, T* __restrict__ Ex, T* __restrict__ Ey,
                                                T* __restrict__ Ez, const T* __restrict__ Hx,
                                                const T* __restrict__ Hy, const T* __restrict__ Hz,
                                                const T* __restrict__ eps_map, const T* __restrict__ sig_map,
                                                const unsigned char* __restrict__ mat,
-                                               const T* __restrict__ mtab, T dt, Src src, Tiles tl) {
+                                               const T* __restrict__ mtab, T dt, Src src, Tiles tl,
+                                               T* __restrict__ Ox, T* __restrict__ Oy, T* __restrict__ Oz) {
   // Edge coefficients of an edge whose four cells share one material,
   // per material id: the same expressions as the general path below (so
   // equal to it bit for bit); mixed edges take the general path.
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(64 * RY) void e_update(Geo g, T* __restrict__ Ex, T
         coef(EV(m_jm_km, e_jm_km), EV(m_km, e_km), EV(cur.m_jm, cur.e_jm), EV(cur.m_c, cur.e_c),
              SV(m_jm_km, s_jm_km), SV(m_km, s_km), SV(cur.m_jm, cur.s_jm), SV(cur.m_c, cur.s_c), ca, cb);
       }
-      Ex[c] = ca * cur.ex + cb * curl;
+      (OOP ? Ox : Ex)[c] = ca * cur.ex + cb * curl;
     }
     if (iin && kin) {  // Ey at (i, j+1/2, k)
       T curl = dq(cur.hx - hx_km, sdz, idz) - dq(cur.hz - cur.hz_im, sdx, idx);
@@ -274,7 +277,7 @@ __global__ __launch_bounds__(64 * RY) void e_update(Geo g, T* __restrict__ Ex, T
         coef(EV(m_im_km, e_im_km), EV(m_km, e_km), EV(cur.m_im, cur.e_im), EV(cur.m_c, cur.e_c),
              SV(m_im_km, s_im_km), SV(m_km, s_km), SV(cur.m_im, cur.s_im), SV(cur.m_c, cur.s_c), ca, cb);
       }
-      Ey[c] = ca * cur.ey + cb * curl;
+      (OOP ? Oy : Ey)[c] = ca * cur.ey + cb * curl;
     }
     if (iin && jin) {  // Ez at (i, j, k+1/2)
       T curl = dq(cur.hy - cur.hy_im, sdx, idx) - dq(cur.hx - cur.hx_jm, sdy, idy);
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(64 * RY) void e_update(Geo g, T* __restrict__ Ex, T
              SV(cur.m_imjm, cur.s_imjm), SV(cur.m_jm, cur.s_jm), SV(cur.m_im, cur.s_im), SV(cur.m_c, cur.s_c),
              ca, cb);
       }
-      Ez[c] = ca * cur.ez + cb * curl;
+      (OOP ? Oz : Ez)[c] = ca * cur.ez + cb * curl;
     }
     hx_km = cur.hx;
     hy_km = cur.hy;

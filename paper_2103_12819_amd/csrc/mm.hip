@@ -933,16 +933,28 @@ mmk::Src make_src(const mm_ctx* c) {
   return src;
 }
 
-// Step 2 of step c->step.
+// Step 2 of step c->step.  With eout (the adjoint's recompute only; no
+// open boundary, no hard sources): E^{n+1} goes to eout, E keeps E^n.
 template <typename T>
-mm_status e_step(mm_ctx* c) {
+mm_status e_step(mm_ctx* c, void* const* eout = nullptr) {
   const Geo g = make_geo(c);
   const mmk::Src src = make_src(c);
   Timed tm(c, 0);
+  if (eout && (c->n_pml > 0 || !c->hard.empty()))
+    return fail(c, MM_ESTATE, "an out-of-place E update needs no open boundary and no hard source");
 #define MM_EUPD1(SIG, MAT, RY, N, LIST)                                                                        \
-  hipLaunchKernelGGL((mmk::e_update<T, SIG, MAT, RY>), dim3(N), dim3(64, RY), 0, c->stream, g, (T*)c->E[0],    \
-                     (T*)c->E[1], (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2],       \
-                     (const T*)c->eps, (const T*)c->sig, c->mat, (const T*)c->mtab, (T)c->dt, src, tiles(c, LIST))
+  do {                                                                                                         \
+    if (eout)                                                                                                  \
+      hipLaunchKernelGGL((mmk::e_update<T, SIG, MAT, RY, true>), dim3(N), dim3(64, RY), 0, c->stream, g,       \
+                         (T*)c->E[0], (T*)c->E[1], (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1],          \
+                         (const T*)c->H[2], (const T*)c->eps, (const T*)c->sig, c->mat, (const T*)c->mtab,      \
+                         (T)c->dt, src, tiles(c, LIST), (T*)eout[0], (T*)eout[1], (T*)eout[2]);                \
+    else                                                                                                       \
+      hipLaunchKernelGGL((mmk::e_update<T, SIG, MAT, RY>), dim3(N), dim3(64, RY), 0, c->stream, g,             \
+                         (T*)c->E[0], (T*)c->E[1], (T*)c->E[2], (const T*)c->H[0], (const T*)c->H[1],          \
+                         (const T*)c->H[2], (const T*)c->eps, (const T*)c->sig, c->mat, (const T*)c->mtab,      \
+                         (T)c->dt, src, tiles(c, LIST), (T*)nullptr, (T*)nullptr, (T*)nullptr);                \
+  } while (0)
 #define MM_EUPD(SIG, MAT)                                                                                      \
   do {                                                                                                         \
     if (c->n_all2 > 0) MM_EUPD1(SIG, MAT, 8, c->n_all2, c->d_tl_all2);                                         \

@@ -1,9 +1,12 @@
 // Reverse-mode (adjoint) kernels of the coupled step, for gradients of the
 // time-integrated Poynting flux L = sum_n dt P^n with respect to the eps_r
-// and Ms cell maps.  The paper has no adjoint; this is the exact reverse of
-// the forward kernels in kernels.h (same iteration counts, the recorded H-M
-// iterates replayed), built from:
-//   * adj_seed_flux       dt dP/dE, dt dP/dH at the probe plane
+// and Ms cell maps.  The paper has no adjoint; this is the reverse of the
+// forward kernels in kernels.h (same iteration counts, the recorded H-M
+// iterates replayed; exact up to rounding, since Step 2's curl term is taken
+// back from the two stored E levels), built from:
+//   * adj_step_open       opens a reverse step: the stored H levels back into
+//                         full-size scratch, and dt dP/dE, dt dP/dH at the
+//                         probe plane
 //   * adj_mag_prep        per magnetic face: b, d, H_eff^s of the sub-step
 //   * adj_mag_iter        reverse of iteration r of the closed-form solve
 //                         (N(M), eq:llg_tra4, a = kappa H_eff - d) giving
@@ -13,13 +16,14 @@
 //                         readers' Q (fixed order, no atomics)
 //   * adj_mag_inv         reverse of b, d, q (eq:llg_tra5/6, eq:iterate_H)
 //   * adj_touch,          reverse of the non-magnetic Faraday update: the
-//     adj_zero_walls      face cotangent T splits into the H^s cotangent and
+//     adj_face_end        face cotangent T splits into the H^s cotangent and
 //                         C = -(dt/2 mu0) T for curl E
 //   * add_curl_h          E_bar += curl H(C) (transpose of curl E), C read
 //                         from the face cotangents as they stand
 //   * adj_e_coef          reverse of Step 2 per edge: E_bar <- ca E_bar,
 //                         W = cb E_bar, d L / d eps_e accumulated
 //   * h_bulk(coef = -1)   H_bar += curl E(W) (transpose of curl H)
+//   * copy_gather         the recompute's per-step stores
 #pragma once
 
 #include "kernels.h"
@@ -51,6 +55,12 @@ __device__ __forceinline__ int adj_family(const AdjMag& a, int t) {
   return t < a.off1 ? 0 : (t < a.off2 ? 1 : 2);
 }
 
+// A face of family f at (p[0], p[1], p[2]) counts in the face pass when it
+// lies in the grid and is interior along its own axis.
+__device__ __forceinline__ bool face_inside(const Geo& g, int f, const int p[3]) {
+  return p[0] < g.nx && p[1] < g.ny && p[2] < g.nz && (((g.per >> f) & 1) || p[f] >= 1);
+}
+
 // Transpose of x = (b + (a.b) a - a x b) / (1 + |a|^2): cotangents of a, b.
 __device__ __forceinline__ void vacus_vjp(const double a[3], const double b[3], const double x[3],
                                           const double xb[3], double ab[3], double bb[3]) {
@@ -67,15 +77,12 @@ __device__ __forceinline__ void vacus_vjp(const double a[3], const double b[3], 
   }
 }
 
-// dt dP/dE and dt dP/dH for the node plane x = i0 (one thread per (j, k)).
+// dt dP/dE and dt dP/dH for the node plane x = i0 at node e = j + NY k.
 template <typename T>
-__global__ __launch_bounds__(256) void adj_seed_flux(Geo g, T* __restrict__ Eby, T* __restrict__ Ebz,
-                                                    T* __restrict__ Hby, T* __restrict__ Hbz,
-                                                    const T* __restrict__ Ey, const T* __restrict__ Ez,
-                                                    const T* __restrict__ Hy, const T* __restrict__ Hz, int i0,
-                                                    double w, int NY, int NZ) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= NY * NZ) return;
+__device__ __forceinline__ void seed_flux_node(const Geo& g, T* __restrict__ Eby, T* __restrict__ Ebz,
+                                               T* __restrict__ Hby, T* __restrict__ Hbz, const T* __restrict__ Ey,
+                                               const T* __restrict__ Ez, const T* __restrict__ Hy,
+                                               const T* __restrict__ Hz, int i0, double w, int NY, int e) {
   const int k = e / NY, j = e - k * NY;
   const int im = dn(i0, g.nx, g.per & 1);
   if (j < g.ny) {   // + Ey * (Hz(i0-1) + Hz(i0)) / 2
@@ -97,14 +104,18 @@ __global__ __launch_bounds__(256) void adj_seed_flux(Geo g, T* __restrict__ Eby,
 }
 
 // b, d and H_eff^s of the sub-step; clears the per-sub-step accumulators.
+// With scat_r >= 1 it also puts magnetic iterate scat_r into A (the
+// full-size array the next reverse iteration's neighbours read).
 template <typename T>
 __global__ __launch_bounds__(256) void adj_mag_prep(Geo g, const T* __restrict__ Hs0, const T* __restrict__ Hs1,
                                                    const T* __restrict__ Hs2, AdjMag a, double H0x, double H0y,
-                                                   double H0z) {
+                                                   double H0z, T* A0, T* A1, T* A2, int scat_r) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n) return;
   const int f = adj_family(a, t);
   const int c = a.idx[t];
+  // (and magnetic iterate scat_r into A for the first reverse iteration's neighbours)
+  if (scat_r >= 1) (f == 0 ? A0 : (f == 1 ? A1 : A2))[c] = (T)a.hlog[(size_t)(scat_r - 1) * a.n + t];
   int i, j, k;
   face_ijk(g, c, i, j, k);
   HRead<T> Rd;
@@ -130,17 +141,6 @@ __global__ __launch_bounds__(256) void adj_mag_prep(Geo g, const T* __restrict__
     a.db[q][t] = 0.0;
   }
   a.qb[t] = 0.0;
-}
-
-// Magnetic iterate r-1 into a full-size array (what iteration r's
-// neighbours read).
-template <typename T>
-__global__ __launch_bounds__(256) void adj_scatter_iter(AdjMag a, T* A0, T* A1, T* A2, int r) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.n) return;
-  const int f = adj_family(a, t);
-  T* A = f == 0 ? A0 : (f == 1 ? A1 : A2);
-  A[a.idx[t]] = (T)a.hlog[(size_t)(r - 1) * a.n + t];
 }
 
 // Reverse of iteration r on every magnetic face.  Writes the cotangent of
@@ -226,8 +226,15 @@ __global__ __launch_bounds__(256) void adj_gather(Geo g, const int* __restrict__
                                                  const unsigned char* __restrict__ tfam,
                                                  const int* __restrict__ tmag, int nt, double* const* Q,
                                                  AdjMag a, T* Xb0, T* Xb1, T* Xb2, T* Gb0, T* Gb1, T* Gb2,
-                                                 int mode) {
+                                                 int mode, T* A0, T* A1, T* A2, int scat_r, T* Hb0, T* Hb1,
+                                                 T* Hb2, int touch) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  // the next iteration's neighbours: magnetic iterate scat_r into A (the
+  // launch covers max(nt, a.n) threads; A is not read here)
+  if (scat_r >= 1 && u < a.n) {
+    const int ft = adj_family(a, u);
+    (ft == 0 ? A0 : (ft == 1 ? A1 : A2))[a.idx[u]] = (T)a.hlog[(size_t)(scat_r - 1) * a.n + u];
+  }
   if (u >= nt) return;
   const int cu = tfam[u];
   const int c = tidx[u];
@@ -271,6 +278,13 @@ __global__ __launch_bounds__(256) void adj_gather(Geo g, const int* __restrict__
     T* G = cu == 0 ? Gb0 : (cu == 1 ? Gb1 : Gb2);
     G[c] = (T)(D(G[c]) + s);
   }
+  // touch: the face pass's first part on this face (adj_touch mode 0), once
+  // X is final (after adj_mag_inv)
+  if (touch && face_inside(g, cu, p)) {
+    T* H = cu == 0 ? Hb0 : (cu == 1 ? Hb1 : Hb2);
+    const T* X = cu == 0 ? Xb0 : (cu == 1 ? Xb1 : Xb2);
+    H[c] = (T)(D(H[c]) + D(X[c]));
+  }
 }
 
 // Reverse of the sub-step invariants q, b, d on every magnetic face.
@@ -307,10 +321,11 @@ __global__ __launch_bounds__(256) void adj_mag_inv(AdjMag a, T* Xb0, T* Xb1, T* 
 // the cotangent of the face's Faraday value; the H^s cotangent becomes
 // T + Gb and C = -(dt/2 mu0) T feeds curl E.  Wall faces (constant) get 0.
 // Xb and Gb are zero off the touched faces, so the pass runs in three
-// parts: adj_touch (mode 0) adds Xb on the touched faces, add_curl_h reads
-// C straight from Hb, adj_touch (mode 1) adds Gb and clears Xb and Gb, and
-// adj_zero_walls clears the wall faces.  A face counts when it lies in the
-// grid (0 <= i < nx, ...) and is interior along its own axis.
+// parts: adj_touch (mode 0, or the last adj_gather with touch) adds Xb on
+// the touched faces, add_curl_h reads C straight from Hb, and adj_face_end
+// adds Gb there (clearing Xb and Gb) and clears the wall faces.  A face
+// counts when it lies in the grid (0 <= i < nx, ...) and is interior along
+// its own axis.
 template <typename T>
 __global__ __launch_bounds__(256) void adj_touch(Geo g, const int* __restrict__ tidx,
                                                 const unsigned char* __restrict__ tfam, int nt, T* Hb0, T* Hb1,
@@ -323,7 +338,7 @@ __global__ __launch_bounds__(256) void adj_touch(Geo g, const int* __restrict__ 
   T* H = f == 0 ? Hb0 : (f == 1 ? Hb1 : Hb2);
   int p[3];
   face_ijk(g, c, p[0], p[1], p[2]);
-  const bool inside = p[0] < g.nx && p[1] < g.ny && p[2] < g.nz && (((g.per >> f) & 1) || p[f] >= 1);
+  const bool inside = face_inside(g, f, p);
   if (mode == 0) {
     if (inside) H[c] = (T)(D(H[c]) + D(X[c]));
   } else {
@@ -333,17 +348,35 @@ __global__ __launch_bounds__(256) void adj_touch(Geo g, const int* __restrict__ 
   }
 }
 
-// Wall faces: Hb of family f is cleared on the plane (axis f) = 0 unless the
-// axis is periodic.  blockIdx.y = f; x runs over the plane's faces.
+// The face pass's end in one launch: blockIdx.y = f < 3 clears Hb of family
+// f on the plane (axis f) = 0 unless the axis is periodic (the wall faces);
+// blockIdx.y = 3 is adj_touch mode 1 on the touched faces (interior ones
+// only, so the two parts write different faces).
 template <typename T>
-__global__ __launch_bounds__(256) void adj_zero_walls(Geo g, T* Hb0, T* Hb1, T* Hb2) {
+__global__ __launch_bounds__(256) void adj_face_end(Geo g, const int* __restrict__ tidx,
+                                                   const unsigned char* __restrict__ tfam, int nt, T* Hb0, T* Hb1,
+                                                   T* Hb2, T* Xb0, T* Xb1, T* Xb2, T* Gb0, T* Gb1, T* Gb2) {
   const int f = blockIdx.y;
-  if ((g.per >> f) & 1) return;
-  const int a = f == 0 ? g.ny : g.nx;   // the plane's first axis (y for f = 0, else x)
-  const int b = f == 2 ? g.ny : g.nz;   // its second (z for f = 0 and 1, y for f = 2)
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)a * b) return;
-  const int u = (int)(e % a), v = (int)(e / a);
+  if (f == 3) {
+    if (e >= nt) return;
+    const int u = (int)e;
+    const int fu = tfam[u], c = tidx[u];
+    T* X = fu == 0 ? Xb0 : (fu == 1 ? Xb1 : Xb2);
+    T* G = fu == 0 ? Gb0 : (fu == 1 ? Gb1 : Gb2);
+    T* H = fu == 0 ? Hb0 : (fu == 1 ? Hb1 : Hb2);
+    int p[3];
+    face_ijk(g, c, p[0], p[1], p[2]);
+    if (face_inside(g, fu, p)) H[c] = (T)(D(H[c]) + D(G[c]));
+    X[c] = (T)0;
+    G[c] = (T)0;
+    return;
+  }
+  if ((g.per >> f) & 1) return;
+  const int na = f == 0 ? g.ny : g.nx;   // the plane's first axis (y for f = 0, else x)
+  const int nb = f == 2 ? g.ny : g.nz;   // its second (z for f = 0 and 1, y for f = 2)
+  if (e >= (long long)na * nb) return;
+  const int u = (int)(e % na), v = (int)(e / na);
   if (f == 0) Hb0[at(g, 0, u, v)] = (T)0;
   else if (f == 1) Hb1[at(g, u, 0, v)] = (T)0;
   else Hb2[at(g, u, v, 0)] = (T)0;
@@ -406,28 +439,50 @@ __global__ __launch_bounds__(256) void copy_batch(CopyBatch b) {
     d[q] = s[q];
 }
 
-// Face values at a list of (family, padded index) entries, to (gather) or
-// from (scatter) a compact array: the per-step H^n storage of the
-// recompute, which the reverse reads only at the faces the magnetic rows
-// touch and on the flux plane's two H planes.
+// The opening of a reverse step in one launch: blockIdx.y = 0 and 1 scatter
+// the compact H^n and H^{n+1/2} into their full-size scratch arrays (list
+// entries only), blockIdx.y = 2 is the flux seed (seed_flux_node), which
+// reads the level n+1 arrays, none of which the scatters write.
 template <typename T>
-__global__ __launch_bounds__(256) void list_gather(const int* __restrict__ idx, const unsigned char* __restrict__ fam,
-                                                  int n, const T* __restrict__ H0, const T* __restrict__ H1,
-                                                  const T* __restrict__ H2, T* __restrict__ out) {
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= n) return;
-  const int f = fam[u];
-  out[u] = (f == 0 ? H0 : (f == 1 ? H1 : H2))[idx[u]];
+__global__ __launch_bounds__(256) void adj_step_open(Geo g, const int* __restrict__ gidx,
+                                                    const unsigned char* __restrict__ gfam, int ng,
+                                                    const T* __restrict__ cn, T* Hn0, T* Hn1, T* Hn2,
+                                                    const T* __restrict__ ch, T* Hh0, T* Hh1, T* Hh2, T* Eby,
+                                                    T* Ebz, T* Hby, T* Hbz, const T* Ey, const T* Ez,
+                                                    const T* Hy, const T* Hz, int i0, double w, int NY, int NZ) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.y < 2) {
+    if (e >= ng) return;
+    const int f = gfam[e];
+    if (blockIdx.y == 0) (f == 0 ? Hn0 : (f == 1 ? Hn1 : Hn2))[gidx[e]] = cn[e];
+    else (f == 0 ? Hh0 : (f == 1 ? Hh1 : Hh2))[gidx[e]] = ch[e];
+    return;
+  }
+  if (e >= NY * NZ) return;
+  seed_flux_node(g, Eby, Ebz, Hby, Hbz, Ey, Ez, Hy, Hz, i0, w, NY, e);
 }
 
+// Per-step stores of the recompute in one launch: blockIdx.y < ncopy are
+// copy_batch's arrays, blockIdx.y = ncopy gathers H at the list entries.
 template <typename T>
-__global__ __launch_bounds__(256) void list_scatter(const int* __restrict__ idx,
-                                                   const unsigned char* __restrict__ fam, int n,
-                                                   const T* __restrict__ in, T* H0, T* H1, T* H2) {
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= n) return;
-  const int f = fam[u];
-  (f == 0 ? H0 : (f == 1 ? H1 : H2))[idx[u]] = in[u];
+__global__ __launch_bounds__(256) void copy_gather(CopyBatch b, int ncopy, const int* __restrict__ gidx,
+                                                  const unsigned char* __restrict__ gfam, int ng,
+                                                  const T* __restrict__ H0, const T* __restrict__ H1,
+                                                  const T* __restrict__ H2, T* __restrict__ out) {
+  const int a = blockIdx.y;
+  if (a < ncopy) {
+    const unsigned long long n = b.words[a];
+    const unsigned long long* __restrict__ s = b.src[a];
+    unsigned long long* __restrict__ d = b.dst[a];
+    for (unsigned long long q = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (unsigned long long)gridDim.x * blockDim.x)
+      d[q] = s[q];
+    return;
+  }
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < ng; u += gridDim.x * blockDim.x) {
+    const int f = gfam[u];
+    out[u] = (f == 0 ? H0 : (f == 1 ? H1 : H2))[gidx[u]];
+  }
 }
 
 // Reverse of Step 2 on every interior edge: with D = eps/dt + sigma/2,

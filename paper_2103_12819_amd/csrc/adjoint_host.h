@@ -368,29 +368,33 @@ mm_status adj_substep(mm_ctx* c, T* const* Hs, const double* Ms0, T* const* Ho, 
   if (c->nmag > 0) {
     mmk::AdjMag a = make_adjmag(c, Ms0, log);
     const int nb = (c->nmag + 255) / 256, tb = (w.nt + 255) / 256;
+    const int gb = (std::max(w.nt, c->nmag) + 255) / 256;
+    // iterate r reads iterate r - 1 of its magnetic neighbours from W: the
+    // scatter of iterate r - 1 rides on the launch before iteration r (the
+    // set-up for r = R, the gather of r + 1 otherwise)
     hipLaunchKernelGGL((mmk::adj_mag_prep<T>), dim3(nb), dim3(256), 0, c->stream, g, Hs[0], Hs[1], Hs[2], a, H0x,
-                       H0y, H0z);
+                       H0y, H0z, Wv[0], Wv[1], Wv[2], R >= 2 ? R - 1 : 0);
     for (int r = R; r >= 1; --r) {
-      if (r >= 2)
-        hipLaunchKernelGGL((mmk::adj_scatter_iter<T>), dim3(nb), dim3(256), 0, c->stream, a, Wv[0], Wv[1], Wv[2],
-                           r - 1);
       hipLaunchKernelGGL((mmk::adj_mag_iter<T>), dim3(nb), dim3(256), 0, c->stream, g, a, Hs[0], Hs[1], Hs[2],
                          Ho[0], Ho[1], Ho[2], Wv[0], Wv[1], Wv[2], Hb[0], Hb[1], Hb[2], w.dQ, r, R, H0x, H0y,
                          H0z);
-      hipLaunchKernelGGL((mmk::adj_gather<T>), dim3(tb), dim3(256), 0, c->stream, g, w.tidx, w.tfam, w.tmag, w.nt,
-                         w.dQ, a, Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], r >= 2 ? 0 : 1);
+      hipLaunchKernelGGL((mmk::adj_gather<T>), dim3(r >= 2 ? gb : tb), dim3(256), 0, c->stream, g, w.tidx, w.tfam,
+                         w.tmag, w.nt, w.dQ, a, Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], r >= 2 ? 0 : 1, Wv[0],
+                         Wv[1], Wv[2], r >= 3 ? r - 2 : 0, Hb[0], Hb[1], Hb[2], 0);
     }
     hipLaunchKernelGGL((mmk::adj_mag_inv<T>), dim3(nb), dim3(256), 0, c->stream, a, Xb[0], Xb[1], Xb[2], w.dQ);
+    // with the face pass's first part (T = Hb + Xb on the touched faces)
     hipLaunchKernelGGL((mmk::adj_gather<T>), dim3(tb), dim3(256), 0, c->stream, g, w.tidx, w.tfam, w.tmag, w.nt,
-                       w.dQ, a, Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], 1);
+                       w.dQ, a, Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], 1, Wv[0], Wv[1], Wv[2], 0, Hb[0],
+                       Hb[1], Hb[2], 1);
     HIPCHECK(c, hipGetLastError());
+  } else if (w.nt > 0) {
+    // the face pass's first part on its own (no magnetic rows ran)
+    hipLaunchKernelGGL((mmk::adj_touch<T>), dim3((w.nt + 255) / 256), dim3(256), 0, c->stream, g, w.tidx, w.tfam,
+                       w.nt, Hb[0], Hb[1], Hb[2], Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], 0);
   }
-  // the face pass: T = Hb + Xb on the touched faces, C = -(dt/2 mu0) T into
-  // curl E's transpose, then Hb = T + Gb and the wall faces cleared
-  const int tb = (w.nt + 255) / 256;
-  if (w.nt > 0)
-    hipLaunchKernelGGL((mmk::adj_touch<T>), dim3(tb), dim3(256), 0, c->stream, g, w.tidx, w.tfam, w.nt, Hb[0],
-                       Hb[1], Hb[2], Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], 0);
+  // then C = -(dt/2 mu0) T into curl E's transpose, Hb = T + Gb and the wall
+  // faces cleared
   HIPCHECK(c, hipGetLastError());
   if (defer) return MM_OK;
   dim3 grid;
@@ -410,12 +414,10 @@ mm_status adj_face_finish(mm_ctx* c) {
   T* Hb[3] = {(T*)w.Hb[0], (T*)w.Hb[1], (T*)w.Hb[2]};
   T* Xb[3] = {(T*)w.Xb[0], (T*)w.Xb[1], (T*)w.Xb[2]};
   T* Gb[3] = {(T*)w.Gb[0], (T*)w.Gb[1], (T*)w.Gb[2]};
-  if (w.nt > 0)
-    hipLaunchKernelGGL((mmk::adj_touch<T>), dim3((w.nt + 255) / 256), dim3(256), 0, c->stream, g, w.tidx, w.tfam,
-                       w.nt, Hb[0], Hb[1], Hb[2], Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2], 1);
-  const long long wall = std::max({(long long)c->ny * c->nz, (long long)c->nx * c->nz, (long long)c->nx * c->ny});
-  hipLaunchKernelGGL((mmk::adj_zero_walls<T>), dim3((unsigned)((wall + 255) / 256), 3), dim3(256), 0, c->stream, g,
-                     Hb[0], Hb[1], Hb[2]);
+  const long long most = std::max({(long long)c->ny * c->nz, (long long)c->nx * c->nz, (long long)c->nx * c->ny,
+                                   (long long)w.nt});
+  hipLaunchKernelGGL((mmk::adj_face_end<T>), dim3((unsigned)((most + 255) / 256), 4), dim3(256), 0, c->stream, g,
+                     w.tidx, w.tfam, w.nt, Hb[0], Hb[1], Hb[2], Xb[0], Xb[1], Xb[2], Gb[0], Gb[1], Gb[2]);
   HIPCHECK(c, hipGetLastError());
   return MM_OK;
 }
@@ -451,18 +453,6 @@ mm_status adj_estep(mm_ctx* c, T* const* En, T* const* E1) {
   hipLaunchKernelGGL((mmk::h_bulk<T, false, 1>), dim3(c->n_all), dim3(64, 4), 0, c->stream, g, Hb[0], Hb[1],
                      Hb[2], (const T*)Wv[0], (const T*)Wv[1], (const T*)Wv[2], (const T*)nullptr, (T)-1, (T)0,
                      tiles(c, c->d_tl_all));
-  HIPCHECK(c, hipGetLastError());
-  return MM_OK;
-}
-
-template <typename T>
-mm_status adj_seed(mm_ctx* c, int i0, void* const* E1, void* const* H1) {
-  AdjWork& w = *c->adjw;
-  Geo g = make_geo(c);
-  const int NY = nodes(c, 1), NZ = nodes(c, 2);
-  hipLaunchKernelGGL((mmk::adj_seed_flux<T>), dim3((NY * NZ + 255) / 256), dim3(256), 0, c->stream, g,
-                     (T*)w.Eb[1], (T*)w.Eb[2], (T*)w.Hb[1], (T*)w.Hb[2], (const T*)E1[1], (const T*)E1[2],
-                     (const T*)H1[1], (const T*)H1[2], i0, c->dt * c->dy * c->dz, NY, NZ);
   HIPCHECK(c, hipGetLastError());
   return MM_OK;
 }
@@ -507,6 +497,31 @@ mm_status adj_list(mm_ctx* c, int i0) {
   return MM_OK;
 }
 
+// The copies of L and, when the list is set, the gather of H at its entries
+// into `out`, in one launch.
+template <typename T>
+mm_status copies_and_gather(mm_ctx* c, const CopyList& L, T* out) {
+  AdjWork& w = *c->adjw;
+  mmk::CopyBatch b;
+  std::memset(&b, 0, sizeof b);
+  size_t most = 0;
+  for (int q = 0; q < L.n; ++q) {
+    b.src[q] = (const unsigned long long*)L.src[q];
+    b.dst[q] = (unsigned long long*)L.dst[q];
+    b.words[q] = L.bytes[q] / 8;
+    most = std::max(most, L.bytes[q] / 8);
+  }
+  const int ng = out ? w.ng : 0;
+  const size_t bx = std::max((most + 1023) / 1024, ((size_t)ng + 255) / 256);
+  const unsigned gx = (unsigned)std::max<size_t>(1, std::min<size_t>(bx, 2048));
+  const int gy = L.n + (ng > 0 ? 1 : 0);
+  if (gy == 0) return MM_OK;
+  hipLaunchKernelGGL((mmk::copy_gather<T>), dim3(gx, gy), dim3(256), 0, c->stream, b, L.n, w.gidx, w.gfam, ng,
+                     (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], out);
+  HIPCHECK(c, hipGetLastError());
+  return MM_OK;
+}
+
 // The live E pointers, put back when this goes out of scope.
 struct KeepE {
   mm_ctx* c;
@@ -538,24 +553,14 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
     {
       CopyList L;
       addM(c, L, w.sM[j], true);
-      if ((s = run_copies(c, L))) return s;
-    }
-    if (w.ng > 0) {
-      hipLaunchKernelGGL((mmk::list_gather<T>), dim3((w.ng + 255) / 256), dim3(256), 0, c->stream, w.gidx, w.gfam,
-                         w.ng, (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], (T*)w.sHc[j]);
-      HIPCHECK(c, hipGetLastError());
+      if ((s = copies_and_gather<T>(c, L, (T*)w.sHc[j]))) return s;
     }
     c->hlog_cur = w.slog[j];
     if ((s = substep<T>(c))) return s;
     {
       CopyList L;
       addM(c, L, w.sMh[j], true);
-      if ((s = run_copies(c, L))) return s;
-    }
-    if (w.ng > 0) {
-      hipLaunchKernelGGL((mmk::list_gather<T>), dim3((w.ng + 255) / 256), dim3(256), 0, c->stream, w.gidx, w.gfam,
-                         w.ng, (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], (T*)w.sHh[j]);
-      HIPCHECK(c, hipGetLastError());
+      if ((s = copies_and_gather<T>(c, L, (T*)w.sHh[j]))) return s;
     }
     void* eo[3] = {arr3<T>(w.sE[j], c, 0), arr3<T>(w.sE[j], c, 1), arr3<T>(w.sE[j], c, 2)};
     if ((s = e_step<T>(c, eo))) return s;
@@ -590,14 +595,17 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
       Hh[a] = arr3<T>(w.Hsc[2], c, a);
       Hn[a] = arr3<T>(w.Hsc[j & 1], c, a);
     }
-    if (w.ng > 0) {
-      hipLaunchKernelGGL((mmk::list_scatter<T>), dim3((w.ng + 255) / 256), dim3(256), 0, c->stream, w.gidx, w.gfam,
-                         w.ng, (const T*)w.sHc[j], Hn[0], Hn[1], Hn[2]);
-      hipLaunchKernelGGL((mmk::list_scatter<T>), dim3((w.ng + 255) / 256), dim3(256), 0, c->stream, w.gidx, w.gfam,
-                         w.ng, (const T*)w.sHh[j], Hh[0], Hh[1], Hh[2]);
+    {
+      // the compact H levels into their scratch arrays, and the flux seed at n+1
+      const Geo g = make_geo(c);
+      const int NY = nodes(c, 1), NZ = nodes(c, 2);
+      const int bx = std::max((w.ng + 255) / 256, (NY * NZ + 255) / 256);
+      hipLaunchKernelGGL((mmk::adj_step_open<T>), dim3(bx, 3), dim3(256), 0, c->stream, g, w.gidx, w.gfam, w.ng,
+                         (const T*)w.sHc[j], Hn[0], Hn[1], Hn[2], (const T*)w.sHh[j], Hh[0], Hh[1], Hh[2],
+                         (T*)w.Eb[1], (T*)w.Eb[2], (T*)w.Hb[1], (T*)w.Hb[2], (const T*)E1[1], (const T*)E1[2],
+                         (const T*)H1[1], (const T*)H1[2], i0, c->dt * c->dy * c->dz, NY, NZ);
       HIPCHECK(c, hipGetLastError());
     }
-    if ((s = adj_seed<T>(c, i0, (void* const*)E1, (void* const*)H1))) return s;
     // Step 3: input (H, M)^{n+1/2}, output H^{n+1}
     if ((s = adj_substep<T>(c, Hh, w.sMh[j], H1, w.slog[j] + lsub, iters[2 * j + 1], true))) return s;
     // Step 2

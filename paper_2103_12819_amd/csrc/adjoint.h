@@ -77,17 +77,19 @@ __device__ __forceinline__ void vacus_vjp(const double a[3], const double b[3], 
   }
 }
 
-// dt dP/dE and dt dP/dH for the node plane x = i0 at node e = j + NY k.
+// dt dP/dE and dt dP/dH for the node plane x = i0 at node e = j + NY k; the
+// level n+1 H of the plane comes from a plane store (see plane_store).
 template <typename T>
 __device__ __forceinline__ void seed_flux_node(const Geo& g, T* __restrict__ Eby, T* __restrict__ Ebz,
                                                T* __restrict__ Hby, T* __restrict__ Hbz, const T* __restrict__ Ey,
-                                               const T* __restrict__ Ez, const T* __restrict__ Hy,
-                                               const T* __restrict__ Hz, int i0, double w, int NY, int e) {
+                                               const T* __restrict__ Ez, const T* __restrict__ P, int i0, double w,
+                                               int NY, int NZ, int e) {
   const int k = e / NY, j = e - k * NY;
   const int im = dn(i0, g.nx, g.per & 1);
+  const long long nn = (long long)NY * NZ;
   if (j < g.ny) {   // + Ey * (Hz(i0-1) + Hz(i0)) / 2
     const int c0 = at(g, i0, j, k), cm = at(g, im, j, k);
-    const double hz = 0.5 * (D(Hz[cm]) + D(Hz[c0]));
+    const double hz = 0.5 * (D(P[nn + e]) + D(P[3 * nn + e]));
     const double ey = D(Ey[c0]);
     Eby[c0] = (T)(D(Eby[c0]) + w * hz);
     Hbz[cm] = (T)(D(Hbz[cm]) + w * 0.5 * ey);
@@ -95,7 +97,7 @@ __device__ __forceinline__ void seed_flux_node(const Geo& g, T* __restrict__ Eby
   }
   if (k < g.nz) {   // - Ez * (Hy(i0-1) + Hy(i0)) / 2
     const int c0 = at(g, i0, j, k), cm = at(g, im, j, k);
-    const double hy = 0.5 * (D(Hy[cm]) + D(Hy[c0]));
+    const double hy = 0.5 * (D(P[e]) + D(P[2 * nn + e]));
     const double ez = D(Ez[c0]);
     Ebz[c0] = (T)(D(Ebz[c0]) - w * hy);
     Hby[cm] = (T)(D(Hby[cm]) - w * 0.5 * ez);
@@ -439,17 +441,71 @@ __global__ __launch_bounds__(256) void copy_batch(CopyBatch b) {
     d[q] = s[q];
 }
 
+// The flux seed's H values at level n+1 on the probe plane, per node
+// e = j + NY k: Hy(im), Hz(im), Hy(i0), Hz(i0) at out[q * NY * NZ + e] (only
+// what the seed reads: Hz where j < ny, Hy where k < nz).  With the capture
+// on (fc.buf set, plane p), nodes whose tile is far take the values the far
+// tiles' fused pass captured at level n+1 (fmask bits 0 and 1, as the flux
+// probe reads them); all others read the fields, which hold level n+1 there.
+template <typename T>
+struct PlaneStore {
+  Geo g;
+  const T* Hy;
+  const T* Hz;
+  FluxCap<T> fc;
+  int p;
+  const unsigned char* fmask;
+  int i0, NY, NZ;
+  T* out;   // null: nothing to store
+};
+
+template <typename T>
+__device__ __forceinline__ void plane_store_node(const PlaneStore<T>& a, int e) {
+  const Geo& g = a.g;
+  const int NY = a.NY, NZ = a.NZ, i0 = a.i0, p = a.p;
+  const FluxCap<T>& fc = a.fc;
+  const T* __restrict__ Hy = a.Hy;
+  const T* __restrict__ Hz = a.Hz;
+  const unsigned char* __restrict__ fmask = a.fmask;
+  T* __restrict__ out = a.out;
+  const int k = e / NY, j = e - k * NY;
+  const int ej = j * NZ + k;   // capture and mask index (z fastest)
+  const int im = dn(i0, g.nx, g.per & 1);
+  const T* cb = fc.buf ? fc.buf + (long long)p * 6 * fc.nn + ej : nullptr;
+  const unsigned m = cb ? (fmask[(long long)p * NY * NZ + ej] & 3u) : 0u;
+  const long long nn = (long long)NY * NZ;
+  T hym = 0, hzm = 0, hy0 = 0, hz0 = 0;
+  if (j < g.ny) {
+    hzm = (m & 2u) ? cb[3 * fc.nn] : Hz[at(g, im, j, k)];
+    hz0 = (m & 1u) ? cb[5 * fc.nn] : Hz[at(g, i0, j, k)];
+  }
+  if (k < g.nz) {
+    hym = (m & 2u) ? cb[2 * fc.nn] : Hy[at(g, im, j, k)];
+    hy0 = (m & 1u) ? cb[4 * fc.nn] : Hy[at(g, i0, j, k)];
+  }
+  out[e] = hym;
+  out[nn + e] = hzm;
+  out[2 * nn + e] = hy0;
+  out[3 * nn + e] = hz0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void plane_store(PlaneStore<T> a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < a.NY * a.NZ) plane_store_node(a, e);
+}
+
 // The opening of a reverse step in one launch: blockIdx.y = 0 and 1 scatter
 // the compact H^n and H^{n+1/2} into their full-size scratch arrays (list
 // entries only), blockIdx.y = 2 is the flux seed (seed_flux_node), which
-// reads the level n+1 arrays, none of which the scatters write.
+// reads E^{n+1} and the plane store, neither of which the scatters write.
 template <typename T>
 __global__ __launch_bounds__(256) void adj_step_open(Geo g, const int* __restrict__ gidx,
                                                     const unsigned char* __restrict__ gfam, int ng,
                                                     const T* __restrict__ cn, T* Hn0, T* Hn1, T* Hn2,
                                                     const T* __restrict__ ch, T* Hh0, T* Hh1, T* Hh2, T* Eby,
                                                     T* Ebz, T* Hby, T* Hbz, const T* Ey, const T* Ez,
-                                                    const T* Hy, const T* Hz, int i0, double w, int NY, int NZ) {
+                                                    const T* __restrict__ P, int i0, double w, int NY, int NZ) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (blockIdx.y < 2) {
     if (e >= ng) return;
@@ -459,17 +515,24 @@ __global__ __launch_bounds__(256) void adj_step_open(Geo g, const int* __restric
     return;
   }
   if (e >= NY * NZ) return;
-  seed_flux_node(g, Eby, Ebz, Hby, Hbz, Ey, Ez, Hy, Hz, i0, w, NY, e);
+  seed_flux_node(g, Eby, Ebz, Hby, Hbz, Ey, Ez, P, i0, w, NY, NZ, e);
 }
 
 // Per-step stores of the recompute in one launch: blockIdx.y < ncopy are
-// copy_batch's arrays, blockIdx.y = ncopy gathers H at the list entries.
+// copy_batch's arrays, blockIdx.y = ncopy gathers H at the list entries (when
+// ng > 0), the last row stores the previous step's plane values (when ps.out
+// is set; the launch comes before anything changes H).
 template <typename T>
 __global__ __launch_bounds__(256) void copy_gather(CopyBatch b, int ncopy, const int* __restrict__ gidx,
                                                   const unsigned char* __restrict__ gfam, int ng,
                                                   const T* __restrict__ H0, const T* __restrict__ H1,
-                                                  const T* __restrict__ H2, T* __restrict__ out) {
+                                                  const T* __restrict__ H2, T* __restrict__ out, PlaneStore<T> ps) {
   const int a = blockIdx.y;
+  if (ps.out && a == (int)gridDim.y - 1) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ps.NY * ps.NZ; e += gridDim.x * blockDim.x)
+      plane_store_node(ps, e);
+    return;
+  }
   if (a < ncopy) {
     const unsigned long long n = b.words[a];
     const unsigned long long* __restrict__ s = b.src[a];

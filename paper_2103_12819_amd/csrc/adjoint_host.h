@@ -28,17 +28,13 @@ struct AdjWork {
   double* epsb[3] = {};
   // per step j of a span: sE[j] = E^{n+1} (written there by the out-of-place
   // E update; E^n of step 0 stays in the live E); sHc, sHh: H^n, H^{n+1/2}
-  // at the list entries only (compact)
-  std::vector<void*> sE, sHc, sHh;
+  // on the touched faces only
+  // (sHc, sHh in the order of the touched-face list); sP: the flux seed's H
+  // values of the plane at level n+1 (see plane_store)
+  std::vector<void*> sE, sHc, sHh, sP;
   std::vector<double*> sM, sMh, slog;
-  // the list sHc holds: the touched faces, then the H_y, H_z faces of the
-  // flux plane's two H planes (for the plane at x node g_i0)
-  std::vector<int> h_tidx;
-  std::vector<unsigned char> h_tfam;
-  int* gidx = nullptr;
-  unsigned char* gfam = nullptr;
-  int ng = 0, gcap = 0, g_i0 = -1;
   void* Hsc[3] = {};                 // full-size H scratch the compact levels are scattered into
+  int cap_p = -1;                    // the loss plane's index in the flux-plane capture
   double *b[3] = {}, *d[3] = {}, *hes[3] = {}, *bb[3] = {}, *db[3] = {}, *Mb[3] = {};
   double *qb = nullptr, *hbit = nullptr, *msf_b = nullptr, *aoms_b = nullptr;
   int* tidx = nullptr;
@@ -278,17 +274,11 @@ mm_status adj_alloc(mm_ctx* c) {
     HIPCHECK(c, hipMemcpy(w->tidx, ti.data(), ti.size() * 4, hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(w->tfam, tf.data(), tf.size(), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMemcpy(w->tmag, tm.data(), tm.size() * 4, hipMemcpyHostToDevice));
-    w->h_tidx = std::move(ti);
-    w->h_tfam = std::move(tf);
   }
-  w->gcap = (int)w->h_tidx.size() + 4 * nodes(c, 1) * nodes(c, 2);
-  w->gidx = (int*)dalloc(c, (size_t)w->gcap * sizeof(int));
-  w->gfam = (unsigned char*)dalloc(c, (size_t)w->gcap);
   for (void*& p : w->Hsc) {
     p = dalloc(c, 3 * fb);
     if (!p) return fail(c, MM_ENOMEM, "adjoint work allocation failed");
   }
-  if (!w->gidx || !w->gfam) return fail(c, MM_ENOMEM, "adjoint work allocation failed");
   for (int q = 1; q * w->K2 < w->K; ++q) {
     void* blk = dalloc(c, state_bytes(c));
     if (!blk) return fail(c, MM_ENOMEM, "inner checkpoint allocation failed");
@@ -296,8 +286,11 @@ mm_status adj_alloc(mm_ctx* c) {
   }
   for (int j = 0; j < w->K2; ++j) {
     void* e = dalloc(c, 3 * fb);
-    void* h = dalloc(c, (size_t)w->gcap * c->esz);
-    void* hh = dalloc(c, (size_t)w->gcap * c->esz);
+    void* h = dalloc(c, (size_t)std::max(w->nt, 1) * c->esz);
+    void* hh = dalloc(c, (size_t)std::max(w->nt, 1) * c->esz);
+    void* pl = dalloc(c, (size_t)4 * nodes(c, 1) * nodes(c, 2) * c->esz);
+    if (!pl) return fail(c, MM_ENOMEM, "adjoint segment storage allocation failed");
+    w->sP.push_back(pl);
     double* m = (double*)dalloc(c, 3 * ntot * 8);
     double* mh = (double*)dalloc(c, 3 * ntot * 8);
     double* lg = (double*)dalloc(c, 2 * (size_t)w->cap * nm * 8);
@@ -457,50 +450,10 @@ mm_status adj_estep(mm_ctx* c, T* const* En, T* const* E1) {
   return MM_OK;
 }
 
-// The compact H list for the flux plane at x node i0: the touched faces,
-// then the H_y and H_z faces of the planes i0 - 1 and i0 (every (j, k) node
-// the seed reads), each once.
-mm_status adj_list(mm_ctx* c, int i0) {
-  AdjWork& w = *c->adjw;
-  if (w.g_i0 == i0) return MM_OK;
-  const size_t ne = c->nelem;
-  std::vector<uint64_t> seen((3 * ne + 63) / 64, 0);
-  std::vector<int> gi;
-  std::vector<unsigned char> gf;
-  gi.reserve(w.gcap);
-  gf.reserve(w.gcap);
-  auto add = [&](int f, size_t pi) {
-    const size_t key = (size_t)f * ne + pi;
-    uint64_t& word = seen[key >> 6];
-    const uint64_t bit = 1ull << (key & 63);
-    if (word & bit) return;
-    word |= bit;
-    gi.push_back((int)pi);
-    gf.push_back((unsigned char)f);
-  };
-  for (size_t u = 0; u < w.h_tidx.size(); ++u) add(w.h_tfam[u], (size_t)w.h_tidx[u]);
-  const int NY = nodes(c, 1), NZ = nodes(c, 2);
-  const int im = (c->per & 1) ? (i0 == 0 ? c->nx - 1 : i0 - 1) : i0 - 1;
-  for (int pl : {im, i0})
-    for (int k = 0; k < NZ; ++k)
-      for (int j = 0; j < NY; ++j) {
-        add(1, pidx(c, pl, j, k));
-        add(2, pidx(c, pl, j, k));
-      }
-  if (gi.size() > (size_t)w.gcap) return fail(c, MM_ESTATE, "adjoint: the compact H list overflows");
-  if (!gi.empty()) {
-    HIPCHECK(c, hipMemcpy(w.gidx, gi.data(), gi.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIPCHECK(c, hipMemcpy(w.gfam, gf.data(), gf.size(), hipMemcpyHostToDevice));
-  }
-  w.ng = (int)gi.size();
-  w.g_i0 = i0;
-  return MM_OK;
-}
-
-// The copies of L and, when the list is set, the gather of H at its entries
+// The copies of L and, when out is set, the gather of H on the touched faces
 // into `out`, in one launch.
 template <typename T>
-mm_status copies_and_gather(mm_ctx* c, const CopyList& L, T* out) {
+mm_status copies_and_gather(mm_ctx* c, const CopyList& L, T* out, const mmk::PlaneStore<T>* ps = nullptr) {
   AdjWork& w = *c->adjw;
   mmk::CopyBatch b;
   std::memset(&b, 0, sizeof b);
@@ -511,13 +464,16 @@ mm_status copies_and_gather(mm_ctx* c, const CopyList& L, T* out) {
     b.words[q] = L.bytes[q] / 8;
     most = std::max(most, L.bytes[q] / 8);
   }
-  const int ng = out ? w.ng : 0;
-  const size_t bx = std::max((most + 1023) / 1024, ((size_t)ng + 255) / 256);
+  const int ng = out ? w.nt : 0;
+  mmk::PlaneStore<T> pst{};
+  if (ps) pst = *ps;
+  const size_t np = ps ? (size_t)pst.NY * pst.NZ : 0;
+  const size_t bx = std::max({(most + 1023) / 1024, ((size_t)ng + 255) / 256, (np + 255) / 256});
   const unsigned gx = (unsigned)std::max<size_t>(1, std::min<size_t>(bx, 2048));
-  const int gy = L.n + (ng > 0 ? 1 : 0);
+  const int gy = L.n + (ng > 0 ? 1 : 0) + (ps ? 1 : 0);
   if (gy == 0) return MM_OK;
-  hipLaunchKernelGGL((mmk::copy_gather<T>), dim3(gx, gy), dim3(256), 0, c->stream, b, L.n, w.gidx, w.gfam, ng,
-                     (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], out);
+  hipLaunchKernelGGL((mmk::copy_gather<T>), dim3(gx, gy), dim3(256), 0, c->stream, b, L.n, w.tidx, w.tfam, ng,
+                     (const T*)c->H[0], (const T*)c->H[1], (const T*)c->H[2], out, pst);
   HIPCHECK(c, hipGetLastError());
   return MM_OK;
 }
@@ -549,14 +505,44 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
   c->step = m0;
   c->substep = (int)(2 * m0);
   c->adj_recompute = true;
+  // The far tiles lag half a step inside the span, as in a forward run: their
+  // Step 3 of one step and Step 1 of the next go in one pass (h_far), which
+  // also captures the flux plane's level n+1 values there.  The touched
+  // faces all lie in near tiles, so the stores below see every level whole.
+  // Lagging saves one pass over the far tiles per step and costs one launch,
+  // so small grids (launch-bound) do without it.
+  const long long far_cells = (long long)c->n_far * 64 * 4 * c->tkc;
+  const bool lag_ok = c->n_far > 0 && c->d_fcap && c->tkc <= mmk::kCapPlanesZ && w.cap_p >= 0 &&
+                      far_cells >= (1ll << 21);
+  const Geo g = make_geo(c);
+  const int NY = nodes(c, 1), NZ = nodes(c, 2);
+  // the plane values of step j (level n+1) are stored by the first launch of
+  // step j + 1, or on their own after the span's last step
+  auto plane_args = [&](int jj, bool captured) {
+    mmk::PlaneStore<T> a{};
+    a.g = g;
+    a.Hy = (const T*)c->H[1];
+    a.Hz = (const T*)c->H[2];
+    a.fc = flux_cap<T>(c, captured);
+    a.p = w.cap_p;
+    a.fmask = c->d_fmask;
+    a.i0 = i0;
+    a.NY = NY;
+    a.NZ = NZ;
+    a.out = (T*)w.sP[jj];
+    return a;
+  };
+  bool lagging = false;
   for (int j = 0; j < len; ++j) {
+    const bool end = j == len - 1;
     {
       CopyList L;
       addM(c, L, w.sM[j], true);
-      if ((s = copies_and_gather<T>(c, L, (T*)w.sHc[j]))) return s;
+      const mmk::PlaneStore<T> pa = plane_args(j - 1, lagging);
+      if ((s = copies_and_gather<T>(c, L, (T*)w.sHc[j], j > 0 ? &pa : nullptr))) return s;
     }
     c->hlog_cur = w.slog[j];
-    if ((s = substep<T>(c))) return s;
+    if ((s = substep<T>(c, lagging))) return s;   // Step 1 (near tiles only when lagging)
     {
       CopyList L;
       addM(c, L, w.sMh[j], true);
@@ -566,7 +552,15 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
     if ((s = e_step<T>(c, eo))) return s;
     for (int a = 0; a < 3; ++a) c->E[a] = eo[a];
     c->hlog_cur = w.slog[j] + lsub;
-    if ((s = substep<T>(c))) return s;
+    const bool lag = lag_ok && !end;
+    if ((s = substep<T>(c, lag, true))) return s;   // Step 3 (near tiles only when lagging on)
+    if (lag && (s = h_far<T>(c, true))) return s;
+    if (end) {
+      hipLaunchKernelGGL((mmk::plane_store<T>), dim3((NY * NZ + 255) / 256), dim3(256), 0, c->stream,
+                         plane_args(j, false));
+      HIPCHECK(c, hipGetLastError());
+    }
+    lagging = lag;
     c->step++;
   }
   for (int a = 0; a < 3; ++a) c->E[a] = live.E[a];
@@ -597,13 +591,11 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
     }
     {
       // the compact H levels into their scratch arrays, and the flux seed at n+1
-      const Geo g = make_geo(c);
-      const int NY = nodes(c, 1), NZ = nodes(c, 2);
-      const int bx = std::max((w.ng + 255) / 256, (NY * NZ + 255) / 256);
-      hipLaunchKernelGGL((mmk::adj_step_open<T>), dim3(bx, 3), dim3(256), 0, c->stream, g, w.gidx, w.gfam, w.ng,
+      const int bx = std::max((w.nt + 255) / 256, (NY * NZ + 255) / 256);
+      hipLaunchKernelGGL((mmk::adj_step_open<T>), dim3(bx, 3), dim3(256), 0, c->stream, g, w.tidx, w.tfam, w.nt,
                          (const T*)w.sHc[j], Hn[0], Hn[1], Hn[2], (const T*)w.sHh[j], Hh[0], Hh[1], Hh[2],
                          (T*)w.Eb[1], (T*)w.Eb[2], (T*)w.Hb[1], (T*)w.Hb[2], (const T*)E1[1], (const T*)E1[2],
-                         (const T*)H1[1], (const T*)H1[2], i0, c->dt * c->dy * c->dz, NY, NZ);
+                         (const T*)w.sP[j], i0, c->dt * c->dy * c->dz, NY, NZ);
       HIPCHECK(c, hipGetLastError());
     }
     // Step 3: input (H, M)^{n+1/2}, output H^{n+1}
@@ -620,7 +612,6 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
 template <typename T>
 mm_status adjoint_run(mm_ctx* c, int i0, double* grad_eps, double* grad_Ms) {
   mm_status s = adj_alloc(c);
-  if (!s) s = adj_list(c, i0);
   if (s) return s;
   AdjWork& w = *c->adjw;
   const size_t fb = c->nelem * c->esz, fd = c->nelem * sizeof(double);
@@ -640,6 +631,18 @@ mm_status adjoint_run(mm_ctx* c, int i0, double* grad_eps, double* grad_Ms) {
   }
   s = copy_state(c, w.fin, true);
   if (s) return s;
+  w.cap_p = -1;
+  {
+    int p = 0;
+    for (const ProbeRec& r : c->probes) {
+      if (r.d.kind == 0) continue;
+      if (r.d.i == i0) {
+        w.cap_p = p;
+        break;
+      }
+      ++p;
+    }
+  }
   // the E slots: the edges the E update never writes (PEC walls) keep their
   // constant values, so every slot starts as a copy of the live E
   for (void* blk : w.sE) {

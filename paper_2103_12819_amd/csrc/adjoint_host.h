@@ -4,9 +4,12 @@
 // Forward: with mm_adjoint_enable(c, K), mm_step saves the state (E, H, M)
 // at every step index that is a multiple of K.
 // mm_adjoint: for each K-step segment, last first, restore its checkpoint
-// and recompute the segment, storing per step E^n, H^n, M^n, H^{n+1/2},
-// M^{n+1/2} and the H iterates of both sub-steps; then reverse the steps
-// (flux seed at n+1, Step 3, Step 2, Step 1) with the kernels of adjoint.h.
+// and recompute the segment, storing per step E^{n+1} (the out-of-place E
+// update writes it there), M^n, M^{n+1/2}, the H iterates of both sub-steps,
+// H^n and H^{n+1/2} on the faces the magnetic rows touch only, and the flux
+// plane's level n+1 H values; then reverse the steps (flux seed at n+1,
+// Step 3, Step 2, Step 1) with the kernels of adjoint.h.  On large grids the
+// far tiles lag half a step in that recompute, as in a forward run.
 // Two-level (inner spacing K2 < K): the segment is first recomputed once,
 // saving the state every K2 steps, and then reversed K2 steps at a time,
 // so only K2 steps of per-step storage are held.

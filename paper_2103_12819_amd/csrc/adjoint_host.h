@@ -532,7 +532,7 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
     a.i0 = i0;
     a.NY = NY;
     a.NZ = NZ;
-    a.out = (T*)w.sP[jj];
+    a.out = jj >= 0 ? (T*)w.sP[jj] : nullptr;
     return a;
   };
   bool lagging = false;
@@ -541,8 +541,8 @@ mm_status reverse_span(mm_ctx* c, int i0, long m0, int len, void* start) {
     {
       CopyList L;
       addM(c, L, w.sM[j], true);
-      const mmk::PlaneStore<T> pa = plane_args(j - 1, lagging);
-      if ((s = copies_and_gather<T>(c, L, (T*)w.sHc[j], j > 0 ? &pa : nullptr))) return s;
+      const mmk::PlaneStore<T> pa = plane_args(j - 1, lagging);   // (none before the first step)
+      if ((s = copies_and_gather<T>(c, L, (T*)w.sHc[j], pa.out ? &pa : nullptr))) return s;
     }
     c->hlog_cur = w.slog[j];
     if ((s = substep<T>(c, lagging))) return s;   // Step 1 (near tiles only when lagging)

@@ -1,0 +1,84 @@
+"""Pin of the oracle's edge permittivity at a material interface: the mean
+of the cells around an edge, our reading of the second-order material
+stencils (Sec. 3.1; Sec. 2 for the update it enters).
+
+A pulse in vacuum meets a half-space of eps_r = 4 at normal incidence.  The
+continuum reflection coefficient is Fresnel's (n1 - n2)/(n1 + n2) = -1/3.
+At Courant number 1 in the vacuum part a discrete wave moves one cell per
+step exactly, so the incident and reflected pulses recorded at a probe
+between source and interface give the discrete reflection coefficient
+R(omega) = F_ref / F_inc * exp(i omega 2 L dt) with no propagation error,
+L the probe's distance to the interface in cells.  With the mean of the two
+cells on either side at the interface edge the scheme is second-order
+accurate there: |R - (-1/3)| falls as (k dx)^2.  An edge that took the
+permittivity of one side only would move the interface by half a cell, a
+first-order phase error of about k dx / 3.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Simulation
+from oracle.yee_llg import EPS0, waveform
+
+NX, XS, XP, XI = 3000, 1000, 1400, 1800   # source, probe, interface nodes
+STEPS, SPLIT = 2000, 800                   # incident before SPLIT, reflected after
+F0 = 20e12
+TP, T0 = 0.3 / F0, 1.5 / F0                # a short pulse: a broad spectrum
+EPS2 = 4.0
+KDX = (0.02, 0.04, 0.08, 0.16)
+
+
+def _probe_series(one_sided=False):
+    d = (1e-6, 1e2, 1e2)
+    dt = W.cfl_dt(1.0, *d)
+    eps = np.ones((1, 1, NX))
+    eps[0, 0, XI:] = EPS2
+    prof = np.zeros(W.edge_shape((NX, 1, 1), (False, True, True), 2))
+    prof[0, 0, XS] = 1.0
+    sim = Simulation((NX, 1, 1), d, dt, eps_r=eps, periodic=(False, True, True), source=(2, prof, F0, TP, T0))
+    if one_sided:   # planted: the interface edge takes the permittivity after it
+        sim.ca[2][XI, :, :] = 1.0
+        sim.cb[2][XI, :, :] = dt / (EPS0 * EPS2)
+    ser = np.zeros(STEPS)
+    for n in range(STEPS):
+        sim.step(1)
+        ser[n] = sim.E[2][XP, 0, 0]
+    return ser, dt
+
+
+def _reflection(ser, dt):
+    # the windows hold the whole pulses (the left-going one returns from the
+    # wall only after step 2400)
+    assert np.max(np.abs(ser[SPLIT - 100:SPLIT])) < 1e-4 * np.max(np.abs(ser))
+    inc = np.where(np.arange(STEPS) < SPLIT, ser, 0.0)
+    ref = np.where(np.arange(STEPS) >= SPLIT, ser, 0.0)
+    w = 2 * np.pi * np.fft.rfftfreq(STEPS, dt)
+    R = np.fft.rfft(ref) / np.fft.rfft(inc) * np.exp(1j * w * 2 * (XI - XP) * dt)
+    kdx = w * dt          # k dx in the vacuum part at Courant number 1
+    out = {}
+    for target in KDX:
+        q = int(np.argmin(np.abs(kdx - target)))
+        out[target] = (float(kdx[q]), complex(R[q]))
+    return out
+
+
+def test_interface_reflection_is_fresnel_to_second_order():
+    ser, dt = _probe_series()
+    R = _reflection(ser, dt)
+    errs = []
+    for target in KDX:
+        k, r = R[target]
+        e = abs(r - (-1.0 / 3.0))
+        errs.append(e)
+        assert e < 0.3 * k * k, (k, r)
+    # the error quadruples when k dx doubles
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 3.0 < e2 / e1 < 5.5, errs
+
+
+def test_planted_one_sided_interface_fails():
+    ser, dt = _probe_series(one_sided=True)
+    R = _reflection(ser, dt)
+    k, r = R[0.04]
+    assert abs(r - (-1.0 / 3.0)) > 0.3 * k * k * 10

@@ -3,7 +3,8 @@ of the cells around an edge, our reading of the second-order material
 stencils (Sec. 3.1; Sec. 2 for the update it enters).
 
 A pulse in vacuum meets a half-space of eps_r = 4 at normal incidence.  The
-continuum reflection coefficient is Fresnel's (n1 - n2)/(n1 + n2) = -1/3.
+continuum reflection coefficient is Fresnel's (n1 - n2)/(n1 + n2) = -1/3
+(and +1/3 for a half-space of mu_r = 4, the impedance doubling instead).
 At Courant number 1 in the vacuum part a discrete wave moves one cell per
 step exactly, so the incident and reflected pulses recorded at a probe
 between source and interface give the discrete reflection coefficient
@@ -29,14 +30,15 @@ EPS2 = 4.0
 KDX = (0.02, 0.04, 0.08, 0.16)
 
 
-def _probe_series(one_sided=False):
+def _probe_series(one_sided=False, which="eps"):
     d = (1e-6, 1e2, 1e2)
     dt = W.cfl_dt(1.0, *d)
-    eps = np.ones((1, 1, NX))
-    eps[0, 0, XI:] = EPS2
+    half = np.ones((1, 1, NX))
+    half[0, 0, XI:] = EPS2
     prof = np.zeros(W.edge_shape((NX, 1, 1), (False, True, True), 2))
     prof[0, 0, XS] = 1.0
-    sim = Simulation((NX, 1, 1), d, dt, eps_r=eps, periodic=(False, True, True), source=(2, prof, F0, TP, T0))
+    maps = {"eps_r": half} if which == "eps" else {"mu_r": half}
+    sim = Simulation((NX, 1, 1), d, dt, periodic=(False, True, True), source=(2, prof, F0, TP, T0), **maps)
     if one_sided:   # planted: the interface edge takes the permittivity after it
         sim.ca[2][XI, :, :] = 1.0
         sim.cb[2][XI, :, :] = dt / (EPS0 * EPS2)
@@ -63,13 +65,17 @@ def _reflection(ser, dt):
     return out
 
 
-def test_interface_reflection_is_fresnel_to_second_order():
-    ser, dt = _probe_series()
+@pytest.mark.parametrize("which,fresnel", [("eps", -1.0 / 3.0), ("mu", 1.0 / 3.0)])
+def test_interface_reflection_is_fresnel_to_second_order(which, fresnel):
+    """eps_r = 4: n2 = 2, R = (1 - 2)/(1 + 2); mu_r = 4: Z2 = 2 Z1, R = (2 - 1)/(2 + 1)
+    (for E).  The tangential H faces lie half a cell off the interface node,
+    so the mu case checks where mu enters (h/mu on the faces of its cell)."""
+    ser, dt = _probe_series(which=which)
     R = _reflection(ser, dt)
     errs = []
     for target in KDX:
         k, r = R[target]
-        e = abs(r - (-1.0 / 3.0))
+        e = abs(r - fresnel)
         errs.append(e)
         assert e < 0.3 * k * k, (k, r)
     # the error quadruples when k dx doubles
